@@ -1,0 +1,193 @@
+"""CPU oracle for the per-event squared matrix element (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the package smoke check
+and by the benchmark's CPU-baseline leg, never by the product path.  It shares
+no code with the HIP library (``paper_2503_21935_amd``) and neither imports
+the other; both read momenta from the separate ``inputs`` module.
+
+Contents
+  * ``sm_params``      derived Standard-Model constants for the workloads
+  * ``colour_matrix``  C_kl = sum over colours of conj(c_k) c_l, by definition,
+                        with explicit Gell-Mann matrices
+  * ``me2``            |M|^2 per event (C routines in ``me_oracle.c``)
+  * ``ordered_amps``   colour-ordered partial amplitudes at one helicity
+  * ``me2_dressed``    |M|^2 by explicit colour brute force (slow; few events)
+
+The paper gives no formulas; the matrix element is the textbook tree-level one
+(its Sec. 2 names the step, Sec. 3 the two parts -- Feynman diagrams, then the
+colour-matrix quadratic form).  Parameter readings: electroweak inputs
+(alpha, G_F, M_Z), so M_W and sin^2(theta_W) are derived; fixed widths;
+T^a = lambda^a / 2; normalisation 1/(spins x colours x identical finals).
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import itertools
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "me_oracle.c")
+_LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_quad.so")}
+
+PROCESS_NGLUON = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
+
+
+def build(force: bool = True) -> None:
+    """Compile the double and __float128 variants with gcc."""
+    for quad, lib in _LIBS.items():
+        if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
+            continue
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-o", lib + ".tmp", _SRC]
+        if quad:
+            cmd[1:1] = ["-DORACLE_QUAD"]
+            cmd += ["-lquadmath"]
+        cmd += ["-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(lib + ".tmp", lib)
+
+
+@functools.lru_cache(maxsize=None)
+def _lib(quad: bool = False):
+    path = _LIBS[quad]
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        build(force=False)
+    lib = ctypes.CDLL(path)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_ee_mumu.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, dp, dp]
+    lib.oracle_ggx.argtypes = [dp, ctypes.c_int64, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, dp, dp]
+    lib.oracle_ggx_amps.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, dp]
+    lib.oracle_ggx_dressed.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       dp, dp]
+    return lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --------------------------------------------------------------------------
+# Parameters
+# --------------------------------------------------------------------------
+
+def sm_params(alpha_s=0.118, inv_alpha=132.507, gf=1.16639e-5, mz=91.188, wz=2.4414, mt=173.0, wt=1.4915):
+    """Derived couplings.  M_W from (alpha, G_F, M_Z):
+    M_W^2 = M_Z^2/2 + sqrt(M_Z^4/4 - pi alpha M_Z^2 / (sqrt2 G_F))."""
+    alpha = 1.0 / inv_alpha
+    mw = math.sqrt(mz ** 2 / 2 + math.sqrt(mz ** 4 / 4 - math.pi * alpha * mz ** 2 / (math.sqrt(2) * gf)))
+    sw2 = 1 - mw ** 2 / mz ** 2
+    return dict(e=math.sqrt(4 * math.pi * alpha), gs=math.sqrt(4 * math.pi * alpha_s), sw2=sw2, mw=mw,
+                mz=mz, wz=wz, mt=mt, wt=wt)
+
+
+# --------------------------------------------------------------------------
+# Colour
+# --------------------------------------------------------------------------
+
+def gell_mann() -> np.ndarray:
+    """T^a = lambda^a / 2, shape [8][3][3]."""
+    l = np.zeros((8, 3, 3), dtype=complex)
+    l[0][0, 1] = l[0][1, 0] = 1
+    l[1][0, 1], l[1][1, 0] = -1j, 1j
+    l[2][0, 0], l[2][1, 1] = 1, -1
+    l[3][0, 2] = l[3][2, 0] = 1
+    l[4][0, 2], l[4][2, 0] = -1j, 1j
+    l[5][1, 2] = l[5][2, 1] = 1
+    l[6][1, 2], l[6][2, 1] = -1j, 1j
+    l[7] = np.diag([1, 1, -2]) / math.sqrt(3)
+    return l / 2
+
+
+def orderings(n: int):
+    """Gluon orderings in the order the oracle and its colour matrix use
+    (lexicographic permutations of gluon labels 0..n-1)."""
+    return list(itertools.permutations(range(n)))
+
+
+@functools.lru_cache(maxsize=None)
+def colour_matrix(n: int) -> np.ndarray:
+    """C_kl = sum_{a_1..a_n, i, j} conj(c_k) c_l with c_k = (T^{a_s1} ... T^{a_sn})_{ij},
+    s = orderings(n)[k]: the plain definition, summed with Gell-Mann matrices."""
+    T = gell_mann()
+    # W[a_1, ..., a_n, i, j] = (T^{a_1} ... T^{a_n})_{ij}
+    W = T
+    for _ in range(n - 1):
+        W = np.einsum("...ij,bjk->...bik", W, T)
+    perms = orderings(n)
+    # c_sigma(a)_{ij} = W[a_{sigma1}, ..., a_{sigma n}]_{ij}; as an array over a this is
+    # W with axis sigma_m moved to position m.
+    rows = []
+    for s in perms:
+        inv = np.argsort(s)
+        rows.append(np.transpose(W, tuple(inv) + (n, n + 1)).reshape(-1))
+    V = np.stack(rows)
+    C = (V.conj() @ V.T).real
+    return C
+
+
+# --------------------------------------------------------------------------
+# Matrix elements
+# --------------------------------------------------------------------------
+
+def _check_mom(mom, npart):
+    mom = np.ascontiguousarray(mom, dtype=np.float64)
+    if mom.ndim != 3 or mom.shape[1:] != (npart, 4):
+        raise ValueError(f"momenta must be [nevt][{npart}][4], got {mom.shape}")
+    return mom
+
+
+def me2(process: str, mom, params=None, quad: bool = False, per_helicity: bool = False):
+    """Spin- and colour-summed/averaged |M|^2 for every event in ``mom``."""
+    p = params or sm_params()
+    lib = _lib(quad)
+    if process == "ee_mumu":
+        mom = _check_mom(mom, 4)
+        n = mom.shape[0]
+        out = np.empty(n)
+        qh = np.empty((n, 16)) if per_helicity else None
+        rc = lib.oracle_ee_mumu(_ptr(mom), n, p["e"], p["sw2"], p["mz"], p["wz"], _ptr(out), _ptr(qh))
+    elif process in PROCESS_NGLUON:
+        ng = PROCESS_NGLUON[process]
+        mom = _check_mom(mom, ng + 2)
+        n = mom.shape[0]
+        C = np.ascontiguousarray(colour_matrix(ng))
+        out = np.empty(n)
+        qh = np.empty((n, 1 << (ng + 2))) if per_helicity else None
+        rc = lib.oracle_ggx(_ptr(mom), n, ng, _ptr(C), p["gs"], p["mt"], p["wt"], _ptr(out), _ptr(qh))
+    else:
+        raise KeyError(process)
+    if rc != 0:
+        raise RuntimeError(f"oracle failed ({rc})")
+    return (out, qh) if per_helicity else out
+
+
+def ordered_amps(n: int, mom1, hel: int, params=None, gauge_gluon: int = -1, quad: bool = False):
+    """Colour-ordered partial amplitudes J[k] (k over ``orderings(n)``) of one event."""
+    p = params or sm_params()
+    mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(n + 2, 4)
+    out = np.empty((math.factorial(n), 2))
+    rc = _lib(quad).oracle_ggx_amps(_ptr(mom1), n, hel, gauge_gluon, p["gs"], p["mt"], p["wt"], _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def me2_dressed(n: int, mom1, params=None, per_helicity: bool = False):
+    """|M|^2 of one event by explicit colour brute force (n <= 4 gluons)."""
+    p = params or sm_params()
+    mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(n + 2, 4)
+    out = np.empty(1)
+    qh = np.empty(1 << (n + 2))
+    rc = _lib(False).oracle_ggx_dressed(_ptr(mom1), n, p["gs"], p["mt"], p["wt"], _ptr(out), _ptr(qh))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return (out[0], qh) if per_helicity else out[0]
