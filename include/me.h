@@ -1,0 +1,121 @@
+/*
+ * me.h -- C ABI of the MI355X matrix-element library (libme.so).
+ *
+ * The library evaluates, for every phase-space point of a batch, the squared
+ * tree-level matrix element |M|^2 of one fixed partonic process: helicity
+ * amplitudes from external and internal wavefunctions for every Feynman
+ * diagram, accumulated into colour-flow amplitudes J, the colour sum
+ * J^dag C J with the process's constant colour matrix, summed over
+ * helicities.  This is the matrix-element step of the paper's event
+ * generator (Sec. 2: random numbers -> momenta -> matrix element, with a
+ * data-parallel, reentrant, stateless multi-event interface; Sec. 3: the
+ * Feynman-diagram code and the colour-matrix quadratic form).
+ *
+ * Conventions shared by every call:
+ *   - Status codes only (ME_OK or a negative ME_E* value); nothing throws,
+ *     aborts or exits across the ABI.  me_last_error() gives a thread-local
+ *     detail string for the last failure on the calling thread.
+ *   - "device pointer" means memory on the current HIP device (e.g. a torch
+ *     tensor's data_ptr()); the caller owns every data buffer.  The context
+ *     owns its constants and scratch and releases them in me_free().
+ *   - Calls that take a stream are asynchronous on that stream (NULL = the
+ *     default stream); results are valid once the stream has synchronised.
+ *   - Momenta are float64, laid out [nevt][npart][4] with components
+ *     (E, px, py, pz) in GeV, particle order as listed for each process.
+ *     Inputs are not validated kinematically; NaN/Inf propagate to NaN
+ *     outputs without trapping.
+ *   - A context is used by one host thread at a time; me_init is thread-safe.
+ */
+#ifndef ME_H
+#define ME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct me_ctx me_ctx;
+
+enum {
+    ME_OK = 0,
+    ME_EINVAL = -1,   /* null pointer, negative size, wrong argument count */
+    ME_EPROCESS = -2, /* unknown process name */
+    ME_EDEVICE = -3,  /* HIP runtime failure (detail in me_last_error) */
+    ME_ENOMEM = -4,   /* device allocation failed */
+    ME_ESTATE = -5    /* call not valid in the context's current state */
+};
+
+enum { ME_FP64 = 0, ME_MIXED = 1 };
+
+/*
+ * me_init -- create a context for one process on the current HIP device.
+ *
+ * process: "ee_mumu"  e+(1) e-(2) -> mu+(3) mu-(4), s-channel photon + Z
+ *          "gg_tt"    g(1) g(2) -> t(3) tbar(4)
+ *          "gg_ttg"   g g -> t tbar g(5)
+ *          "gg_ttgg"  g g -> t tbar g(5) g(6)
+ *          "gg_ttggg" g g -> t tbar g(5) g(6) g(7)
+ * couplings: host array {alpha_s, 1/alpha, G_F}, n_couplings == 3
+ *            (e.g. {0.118, 132.507, 1.16639e-5}); M_W and sin^2(theta_W)
+ *            follow from (alpha, G_F, M_Z).
+ * masses:    host array {M_Z, W_Z, M_top, W_top} in GeV, n_masses == 4
+ *            (e.g. {91.188, 2.4414, 173.0, 1.4915}); the top width sits on
+ *            every internal top line.
+ * out_ctx:   receives the new context.
+ *
+ * Runs the helicity filter once: every helicity combination is evaluated in
+ * float64 on a few fixed probe points and those whose contribution is exactly
+ * zero on all of them are dropped from later evaluations.  Synchronises the
+ * device.  Errors: ME_EINVAL, ME_EPROCESS, ME_EDEVICE, ME_ENOMEM.
+ */
+int me_init(const char *process, const double *couplings, int n_couplings, const double *masses, int n_masses,
+            me_ctx **out_ctx);
+
+/*
+ * me_eval -- |M|^2 for nevt points.
+ * momenta: device pointer, float64 [nevt][npart][4].
+ * out_me2: device pointer, float64 [nevt]; receives |M|^2 summed over final
+ *          and averaged over initial helicities and colours, divided by the
+ *          number of permutations of identical final-state gluons.
+ * stream:  hipStream_t (NULL = default stream); no host synchronisation.
+ * nevt == 0 launches nothing.  Errors: ME_EINVAL (null pointer, nevt < 0),
+ * ME_EDEVICE (launch failure).
+ */
+int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, void *stream);
+
+/*
+ * me_eval_helicities -- per-helicity contributions, for checks.
+ * out_qhel: device pointer, float64 [nevt][nhel]; entry h receives
+ *           J_h^dag C J_h (before averaging) for every helicity combination
+ *           h in 0..nhel-1 (particle i has helicity + when bit (npart-1-i)
+ *           of h is set), including those the filter dropped.
+ * out_me2:  as in me_eval, but summed over all helicities (no filter).
+ */
+int me_eval_helicities(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, double *out_qhel,
+                       void *stream);
+
+/*
+ * me_info -- static properties of the context's process.
+ * Any output pointer may be NULL.  flops_per_event: the algorithmic
+ * floating-point operation count of one event over the good helicities
+ * (diagram program + colour sum; FMA counted as two operations).
+ */
+int me_info(const me_ctx *ctx, int *npart, int *ndiag, int *ncol, int *nhel, int *nhel_good,
+            double *flops_per_event);
+
+/* me_good_helicities -- copy the filtered helicity indices (host array of at
+ * least nhel ints); *count receives how many there are. */
+int me_good_helicities(const me_ctx *ctx, int *out, int *count);
+
+/* me_free -- release the context (NULL is allowed). Synchronises the device. */
+int me_free(me_ctx *ctx);
+
+const char *me_strerror(int status);
+const char *me_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ME_H */

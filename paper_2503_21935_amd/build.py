@@ -1,0 +1,120 @@
+"""Build libme.so for gfx950.
+
+Steps: run the process generator into ``csrc/gen/``, write one translation
+unit per process and the process table, compile each with hipcc
+(``--offload-arch=gfx950``) and link the shared library in-tree.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+GEN = os.path.join(CSRC, "gen")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libme.so")
+
+PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIPFLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-variable",
+    "-Wno-unused-function", "-Wno-unknown-pragmas",
+    # keep the compiler from forming packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", CSRC,
+]
+
+_TU = """// Generated translation unit: kernels of {name}.
+#include "me_kernels.h"
+{include}
+
+static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                             const me_params& prm, double* qhel, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL(({kernel}<{proc}, double>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
+                       qhel);
+    return hipGetLastError();
+}}
+
+#ifndef __HIP_DEVICE_COMPILE__  // the table entry holds a host function pointer
+extern const me_process_desc me_desc_{name} = {{
+    "{name}", {kind}, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
+    {proc}::flops_amp, {proc}::flops_colour, launch_f64}};
+#endif
+"""
+
+_REG = """// Generated process table.
+#include <cstring>
+#include "me_launch.h"
+{decls}
+static const me_process_desc* const table[] = {{{ptrs}}};
+
+const me_process_desc* me_find_process(const char* name) {{
+    for (const me_process_desc* d : table)
+        if (std::strcmp(d->name, name) == 0) return d;
+    return nullptr;
+}}
+"""
+
+
+def _write(path, text):
+    old = open(path).read() if os.path.exists(path) else None
+    if old != text:
+        with open(path, "w") as f:
+            f.write(text)
+
+
+def generate_sources(processes):
+    sys.path.insert(0, os.path.dirname(HERE))
+    from paper_2503_21935_amd.gen import generate
+
+    info = generate(GEN, [p for p in processes if p.startswith("gg_")])
+    tus = []
+    for name in processes:
+        if name == "ee_mumu":
+            inc, kernel, proc, kind = "", "k_me_ee", "proc_ee_mumu", "ME_KIND_EE"
+        else:
+            inc, kernel, proc, kind = f'#include "gen/proc_{name}.h"', "k_me_gg", f"proc_{name}", "ME_KIND_GG"
+        path = os.path.join(GEN, f"tu_{name}.hip")
+        _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind))
+        tus.append(path)
+    decls = "\n".join(f"extern const me_process_desc me_desc_{n};" for n in processes)
+    ptrs = ", ".join(f"&me_desc_{n}" for n in processes)
+    reg = os.path.join(GEN, "registry.cpp")
+    _write(reg, _REG.format(decls=decls, ptrs=ptrs))
+    return tus + [reg, os.path.join(CSRC, "me_api.cpp")], info
+
+
+def _compile(src):
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
+    cmd = [HIPCC] + HIPFLAGS + lang + ["-c", src, "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-4000:]}")
+    return obj
+
+
+def build(processes=None, jobs: int = 8, verbose: bool = True):
+    processes = processes or PROCESSES
+    os.makedirs(GEN, exist_ok=True)
+    os.makedirs(OBJ, exist_ok=True)
+    srcs, info = generate_sources(processes)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs))
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"built {LIB}")
+    return info
+
+
+if __name__ == "__main__":
+    procs = sys.argv[1:] or None
+    build(procs)

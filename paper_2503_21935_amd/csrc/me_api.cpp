@@ -1,0 +1,258 @@
+// me_api.cpp -- C ABI of libme.so: contexts, helicity filter, launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/me.h"
+#include "me_launch.h"
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_CHECK(expr)                                                                          \
+    do {                                                                                         \
+        hipError_t _e = (expr);                                                                  \
+        if (_e != hipSuccess) return fail(ME_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+struct me_ctx {
+    const me_process_desc* proc;
+    me_params prm;
+    int device;
+    int nhel_good;
+    std::vector<int> good;  // host copy of the filtered helicities
+    int* d_good;            // device copy
+    int* d_all;             // device list 0..nhel-1
+};
+
+// ---------------------------------------------------------------------------
+// Probe points for the helicity filter: flat massless n-body momenta from a
+// fixed splitmix64 stream, rescaled to the final-state masses (the RAMBO
+// construction of Kleiss, Stirling and Ellis).  Generic points: a helicity
+// that vanishes on all of them vanishes identically.
+// ---------------------------------------------------------------------------
+static double probe_uniform(uint64_t& s) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+static void probe_points(const me_process_desc* pd, double roots, const double* masses, int npts,
+                         std::vector<double>& out) {
+    const int nf = pd->npart - 2;
+    out.assign((size_t)npts * pd->npart * 4, 0.0);
+    uint64_t seed = 0x1234567ull;
+    for (int e = 0; e < npts; ++e) {
+        std::vector<double> q(nf * 4);
+        double Q[4] = {0, 0, 0, 0};
+        for (int i = 0; i < nf; ++i) {
+            double c = 2 * probe_uniform(seed) - 1, ph = 2 * M_PI * probe_uniform(seed);
+            double q0 = -std::log(probe_uniform(seed) * probe_uniform(seed));
+            double st = std::sqrt(1 - c * c);
+            double v[4] = {q0, q0 * st * std::cos(ph), q0 * st * std::sin(ph), q0 * c};
+            for (int m = 0; m < 4; ++m) {
+                q[4 * i + m] = v[m];
+                Q[m] += v[m];
+            }
+        }
+        double M = std::sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+        double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M}, x = roots / M, g = Q[0] / M, a = 1 / (1 + g);
+        std::vector<double> p(nf * 4);
+        for (int i = 0; i < nf; ++i) {
+            double bq = b[0] * q[4 * i + 1] + b[1] * q[4 * i + 2] + b[2] * q[4 * i + 3];
+            p[4 * i] = x * (g * q[4 * i] + bq);
+            for (int k = 0; k < 3; ++k) p[4 * i + 1 + k] = x * (q[4 * i + 1 + k] + b[k] * q[4 * i] + a * bq * b[k]);
+        }
+        // rescale 3-momenta so that energies with masses add up to roots
+        double xi = 0.9;
+        for (int it = 0; it < 100; ++it) {
+            double f = -roots, df = 0;
+            for (int i = 0; i < nf; ++i) {
+                double en = std::sqrt(masses[i] * masses[i] + xi * xi * p[4 * i] * p[4 * i]);
+                f += en;
+                df += xi * p[4 * i] * p[4 * i] / en;
+            }
+            xi -= f / df;
+        }
+        double* o = &out[(size_t)e * pd->npart * 4];
+        o[0] = roots / 2;
+        o[3] = roots / 2;
+        o[4] = roots / 2;
+        o[7] = -roots / 2;
+        for (int i = 0; i < nf; ++i) {
+            double* oi = o + 4 * (2 + i);
+            for (int k = 1; k < 4; ++k) oi[k] = xi * p[4 * i + k];
+            oi[0] = std::sqrt(masses[i] * masses[i] + oi[1] * oi[1] + oi[2] * oi[2] + oi[3] * oi[3]);
+        }
+    }
+}
+
+static int helicity_filter(me_ctx* c) {
+    const me_process_desc* pd = c->proc;
+    const int npts = 16;
+    std::vector<double> fm(pd->npart - 2, 0.0);
+    double roots = 13000.0;
+    if (pd->kind == ME_KIND_EE) {
+        roots = 500.0;
+    } else {
+        fm[0] = fm[1] = c->prm.mt;
+    }
+    std::vector<double> pts;
+    probe_points(pd, roots, fm.data(), npts, pts);
+    double *d_mom = nullptr, *d_out = nullptr, *d_q = nullptr;
+    HIP_CHECK(hipMalloc(&d_mom, pts.size() * sizeof(double)));
+    HIP_CHECK(hipMalloc(&d_out, npts * sizeof(double)));
+    HIP_CHECK(hipMalloc(&d_q, (size_t)npts * pd->nhel * sizeof(double)));
+    HIP_CHECK(hipMemcpy(d_mom, pts.data(), pts.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_CHECK(pd->launch_f64(d_mom, npts, d_out, c->d_all, pd->nhel, c->prm, d_q, nullptr));
+    std::vector<double> q((size_t)npts * pd->nhel);
+    HIP_CHECK(hipMemcpy(q.data(), d_q, q.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_CHECK(hipFree(d_mom));
+    HIP_CHECK(hipFree(d_out));
+    HIP_CHECK(hipFree(d_q));
+    c->good.clear();
+    for (int h = 0; h < pd->nhel; ++h) {
+        bool nz = false;
+        for (int e = 0; e < npts; ++e) nz |= (q[(size_t)e * pd->nhel + h] != 0.0);
+        if (nz) c->good.push_back(h);
+    }
+    c->nhel_good = (int)c->good.size();
+    HIP_CHECK(hipMalloc(&c->d_good, std::max(1, c->nhel_good) * sizeof(int)));
+    if (c->nhel_good)
+        HIP_CHECK(hipMemcpy(c->d_good, c->good.data(), c->nhel_good * sizeof(int), hipMemcpyHostToDevice));
+    return ME_OK;
+}
+
+extern "C" {
+
+int me_init(const char* process, const double* couplings, int n_couplings, const double* masses, int n_masses,
+            me_ctx** out_ctx) {
+    if (!process || !couplings || !masses || !out_ctx) return fail(ME_EINVAL, "null argument");
+    if (n_couplings != 3 || n_masses != 4)
+        return fail(ME_EINVAL, "expected 3 couplings {alpha_s, 1/alpha, G_F} and 4 masses {MZ, WZ, MT, WT}");
+    const me_process_desc* pd = me_find_process(process);
+    if (!pd) return fail(ME_EPROCESS, std::string("unknown process ") + process);
+    const double alpha_s = couplings[0], alpha = 1.0 / couplings[1], gf = couplings[2];
+    const double mz = masses[0], wz = masses[1], mt = masses[2], wt = masses[3];
+    if (!(alpha_s > 0) || !(alpha > 0) || !(gf > 0) || !(mz > 0) || !(wz >= 0) || !(mt >= 0) || !(wt >= 0))
+        return fail(ME_EINVAL, "couplings and masses must be positive");
+    // M_W from (alpha, G_F, M_Z); then sin^2 theta_W = 1 - M_W^2/M_Z^2.
+    const double disc = mz * mz * mz * mz / 4 - M_PI * alpha * mz * mz / (std::sqrt(2.0) * gf);
+    if (!(disc > 0)) return fail(ME_EINVAL, "(alpha, G_F, M_Z) admit no real M_W");
+    const double mw = std::sqrt(mz * mz / 2 + std::sqrt(disc));
+    const double sw2 = 1 - mw * mw / (mz * mz);
+    me_ctx* c = new (std::nothrow) me_ctx();
+    if (!c) return fail(ME_ENOMEM, "host allocation");
+    c->proc = pd;
+    c->prm.gs = std::sqrt(4 * M_PI * alpha_s);
+    c->prm.mt = mt;
+    c->prm.wt = wt;
+    c->prm.e = std::sqrt(4 * M_PI * alpha);
+    c->prm.gz = c->prm.e / std::sqrt(sw2 * (1 - sw2));
+    c->prm.gl = -0.5 + sw2;
+    c->prm.gr = sw2;
+    c->prm.mz = mz;
+    c->prm.wz = wz;
+    c->d_good = nullptr;
+    c->d_all = nullptr;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(ME_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    std::vector<int> all(pd->nhel);
+    for (int h = 0; h < pd->nhel; ++h) all[h] = h;
+    if (hipMalloc(&c->d_all, pd->nhel * sizeof(int)) != hipSuccess ||
+        hipMemcpy(c->d_all, all.data(), pd->nhel * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+        me_free(c);
+        return fail(ME_ENOMEM, "device allocation of the helicity table");
+    }
+    int rc = helicity_filter(c);
+    if (rc != ME_OK) {
+        std::string keep = g_last_error;
+        me_free(c);
+        g_last_error = keep;
+        return rc;
+    }
+    *out_ctx = c;
+    return ME_OK;
+}
+
+int me_eval(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, void* stream) {
+    if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
+    if (nevt == 0) return ME_OK;
+    if (!momenta || !out_me2) return fail(ME_EINVAL, "null buffer");
+    if (nevt > (int64_t)ME_BLOCK * 0x7fffffffLL) return fail(ME_EINVAL, "nevt too large for one launch");
+    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr,
+                                  (hipStream_t)stream));
+    return ME_OK;
+}
+
+int me_eval_helicities(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, double* out_qhel,
+                       void* stream) {
+    if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
+    if (nevt == 0) return ME_OK;
+    if (!momenta || !out_me2 || !out_qhel) return fail(ME_EINVAL, "null buffer");
+    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_all, c->proc->nhel, c->prm, out_qhel,
+                                  (hipStream_t)stream));
+    return ME_OK;
+}
+
+int me_info(const me_ctx* c, int* npart, int* ndiag, int* ncol, int* nhel, int* nhel_good, double* flops) {
+    if (!c) return fail(ME_EINVAL, "null context");
+    const me_process_desc* pd = c->proc;
+    if (npart) *npart = pd->npart;
+    if (ndiag) *ndiag = pd->ndiag;
+    if (ncol) *ncol = pd->ncol;
+    if (nhel) *nhel = pd->nhel;
+    if (nhel_good) *nhel_good = c->nhel_good;
+    if (flops) *flops = c->nhel_good * (pd->flops_amp + pd->flops_colour);
+    return ME_OK;
+}
+
+int me_good_helicities(const me_ctx* c, int* out, int* count) {
+    if (!c || !count) return fail(ME_EINVAL, "null argument");
+    *count = c->nhel_good;
+    if (out)
+        for (int i = 0; i < c->nhel_good; ++i) out[i] = c->good[i];
+    return ME_OK;
+}
+
+int me_free(me_ctx* c) {
+    if (!c) return ME_OK;
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    if (c->d_good) e1 = hipFree(c->d_good);
+    if (c->d_all) e2 = hipFree(c->d_all);
+    delete c;
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(ME_EDEVICE, "hipFree failed");
+    return ME_OK;
+}
+
+const char* me_strerror(int status) {
+    switch (status) {
+        case ME_OK: return "ok";
+        case ME_EINVAL: return "invalid argument";
+        case ME_EPROCESS: return "unknown process";
+        case ME_EDEVICE: return "HIP runtime error";
+        case ME_ENOMEM: return "out of memory";
+        case ME_ESTATE: return "invalid state";
+        default: return "unknown status";
+    }
+}
+
+const char* me_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// me_kernels.h -- the per-event |M|^2 kernels (one event per lane).
+//
+// For each event the kernel loads its momenta, loops over the helicity
+// combinations handed in, builds the external wavefunctions, runs the
+// process's generated diagram program into the colour-flow amplitudes J,
+// takes the colour sum J^dag C J and accumulates over helicities (the
+// matrix-element step of the paper, Sec. 2-3).  The result is averaged over
+// initial spins and colours and divided by the identical-particle factor.
+#pragma once
+#include "me_launch.h"
+
+template <int NPART>
+MEV int helicity_of(int h, int i) {
+    return ((h >> (NPART - 1 - i)) & 1) ? 1 : -1;
+}
+
+template <typename T>
+MEV void opaque_mom(mom4<T>& q) {
+    asm volatile("" : "+v"(q.e), "+v"(q.x), "+v"(q.y), "+v"(q.z));
+}
+
+template <typename T>
+MEV void opaque(mom4<T>* p, int n) {
+#pragma unroll
+    for (int i = 0; i < n; ++i) opaque_mom(p[i]);
+}
+
+template <typename T, int NP>
+MEV void load_event(const double* __restrict__ mom, int64_t ev, mom4<T>* p) {
+    const double2* pe = reinterpret_cast<const double2*>(mom + ev * (NP * 4));
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        const double2 a = pe[2 * i], b = pe[2 * i + 1];
+        p[i] = mom4<T>{T(a.x), T(a.y), T(b.x), T(b.y)};
+    }
+}
+
+// qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
+// filter and for tests; entries of helicities not in the list are untouched.
+template <class P, typename T>
+__global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ mom, int64_t nevt,
+                                                    double* __restrict__ out, const int* __restrict__ hels,
+                                                    int nh, me_params prm, double* __restrict__ qhel) {
+    const int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ev >= nevt) return;
+    constexpr int NP = P::npart, NG = P::ngluon;
+    mom4<T> p[NP];
+    load_event<T, NP>(mom, ev, p);
+    gg_ext<T, NG> x;
+    x.m = T(prm.mt);
+    x.mw = T(prm.mt * prm.wt);
+    x.g = T(prm.gs);
+    x.p3 = p[2];
+    x.p4 = p[3];
+#pragma unroll
+    for (int a = 0; a < NG; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
+    T acc = T(0);
+#pragma unroll 1
+    for (int ih = 0; ih < nh; ++ih) {
+        const int h = hels[ih];
+        // Make the momenta opaque to the optimiser in every iteration: the
+        // helicity-independent subexpressions (subset momenta, propagator
+        // denominators) are then recomputed per helicity instead of being
+        // hoisted out of the loop, where they would occupy registers for the
+        // whole loop and force spills.
+        opaque(p, NP);
+        opaque_mom(x.p3);
+        opaque_mom(x.p4);
+#pragma unroll
+        for (int a = 0; a < NG; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
+#pragma unroll
+        for (int a = 0; a < NG; ++a) {
+            const int ip = (a < 2) ? a : a + 2;
+            x.eps[a] = gluon_eps(p[ip], helicity_of<NP>(h, ip), a >= 2);
+        }
+        x.ubar3 = bar(u_spinor(p[2], x.m, helicity_of<NP>(h, 2)));
+        x.v4 = v_spinor(p[3], x.m, helicity_of<NP>(h, 3));
+        cx<T> J[P::ncol];
+#pragma unroll
+        for (int k = 0; k < P::ncol; ++k) J[k] = mk(T(0), T(0));
+        P::template amps<T>(x, J);
+        const T q = P::template colour_sum<T>(J);
+        if (qhel) qhel[ev * P::nhel + h] = double(q) / P::lcd;
+        acc += q;
+    }
+    out[ev] = double(acc) * (1.0 / (256.0 * P::identical * P::lcd));
+}
+
+template <class P, typename T>
+__global__ __launch_bounds__(ME_BLOCK) void k_me_ee(const double* __restrict__ mom, int64_t nevt,
+                                                    double* __restrict__ out, const int* __restrict__ hels,
+                                                    int nh, me_params prm, double* __restrict__ qhel) {
+    const int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ev >= nevt) return;
+    mom4<T> p[P::npart];
+    load_event<T, P::npart>(mom, ev, p);
+    T acc = T(0);
+    for (int ih = 0; ih < nh; ++ih) {
+        const int h = hels[ih];
+        const T q = P::template me_hel<T>(p, h, prm);
+        if (qhel) qhel[ev * P::nhel + h] = double(q);
+        acc += q;
+    }
+    out[ev] = double(acc) * 0.25;
+}

@@ -1,0 +1,70 @@
+// me_process.h -- per-event external state and the e+ e- -> mu+ mu- program.
+#pragma once
+#include "me_vertex.h"
+
+// Physics constants handed to every kernel by value.
+struct me_params {
+    double gs;              // strong coupling sqrt(4 pi alpha_s)
+    double mt, wt;          // top mass and width
+    double e;               // electromagnetic coupling sqrt(4 pi alpha)
+    double gz, gl, gr;      // Z coupling e/(sw cw) and chiral charges of charged leptons
+    double mz, wz;          // Z mass and width
+};
+
+// External wavefunctions and momenta of one event at one helicity for
+// g g -> t tbar + (NG-2) g.  Gluon momenta are counted as flowing into the
+// diagram (q = p for the two incoming gluons, q = -p for outgoing ones).
+template <typename T, int NG>
+struct gg_ext {
+    vec4<T> eps[NG];
+    mom4<T> q[NG];
+    spinor<T> ubar3, v4;
+    mom4<T> p3, p4;
+    T m, mw, g;  // top mass, mass * width, strong coupling
+};
+
+// e+(p1) e-(p2) -> mu+(p3) mu-(p4) through an s-channel photon and Z:
+//   M = (eQ)^2 (Je.Jm)/s + gz^2 [Je'.Jm' - (Je'.k)(Jm'.k)/MZ^2] / (s - MZ^2 + i MZ WZ),
+// with Je = vbar(p1) gamma u(p2), Jm = ubar(p4) gamma v(p3), primes for the
+// chiral Z couplings (gl on the left-handed part, gr on the right-handed part).
+struct proc_ee_mumu {
+    static constexpr int npart = 4;
+    static constexpr int ncol = 1;
+    static constexpr int nhel = 16;
+    static constexpr int lcd = 1;
+    static constexpr int identical = 1;
+    // external spinors 4 x 40, two split currents 2 x 72, contraction and propagators
+    static constexpr double flops_amp = 4 * 40 + 2 * 72 + 4 * 30 + 16 + 60;
+    static constexpr double flops_colour = 3;
+    static constexpr int n_amplitudes = 2;
+    static constexpr int ndiag = 2;
+
+    template <typename T>
+    static MEV T me_hel(const mom4<T>* p, int hel, const me_params& prm) {
+        auto lam = [&](int i) { return ((hel >> (3 - i)) & 1) ? 1 : -1; };
+        const T zero = T(0);
+        spinor<T> vb1 = bar(v_spinor(p[0], zero, lam(0)));
+        spinor<T> u2 = u_spinor(p[1], zero, lam(1));
+        spinor<T> v3 = v_spinor(p[2], zero, lam(2));
+        spinor<T> ub4 = bar(u_spinor(p[3], zero, lam(3)));
+        vec4<T> eL, eR, mL, mR;
+        fbar_gamma_f_lr(vb1, u2, eL, eR);
+        fbar_gamma_f_lr(ub4, v3, mL, mR);
+        const mom4<T> k = p[0] + p[1];
+        const T s = msq(k);
+        const T e = T(prm.e), gz = T(prm.gz), gl = T(prm.gl), gr = T(prm.gr), mz = T(prm.mz);
+        vec4<T> je, jm, jez, jmz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            je.v[c] = eL.v[c] + eR.v[c];
+            jm.v[c] = mL.v[c] + mR.v[c];
+            jez.v[c] = gl * eL.v[c] + gr * eR.v[c];
+            jmz.v[c] = gl * mL.v[c] + gr * mR.v[c];
+        }
+        const cx<T> a_gamma = (e * e / s) * dot(je, jm);  // (eQ)^2 with Q = -1
+        const cx<T> prop_z = crecip(s - mz * mz, mz * T(prm.wz));
+        const cx<T> kz = dot(jez, jmz) - dot(k, jez) * dot(k, jmz) * (T(1) / (mz * mz));
+        const cx<T> a = a_gamma + (gz * gz) * (prop_z * kz);
+        return a.r * a.r + a.i * a.i;
+    }
+};

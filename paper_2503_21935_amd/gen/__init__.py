@@ -1,0 +1,34 @@
+"""Process generator: Feynman diagrams, colour decomposition and HIP emission.
+
+``generate(outdir)`` writes one header per process into ``outdir``.  It runs
+at build time on the host; nothing here is imported on the GPU path at run
+time except the static tables that ``info()`` reports.
+"""
+from __future__ import annotations
+
+import os
+
+from .emit import GGEmitter
+
+GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
+# Maximum number of wavefunctions kept alive at once by the emitted program
+# (more are recomputed): chosen so that the float64 kernels keep their working
+# set in registers without scratch spills.
+LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 6, "gg_ttggg": 6}
+
+
+def generate(outdir: str, processes=None, merge: bool = True) -> dict:
+    os.makedirs(outdir, exist_ok=True)
+    info = {}
+    for name, n in GG_PROCESSES.items():
+        if processes and name not in processes:
+            continue
+        em = GGEmitter(name, n, merge=merge, cap=LIVE_CAP[name])
+        src = em.render()
+        path = os.path.join(outdir, f"proc_{name}.h")
+        old = open(path).read() if os.path.exists(path) else None
+        if old != src:
+            with open(path, "w") as f:
+                f.write(src)
+        info[name] = dict(em.plan.stats(), lcd=em.lcd, ncol=len(em.perms))
+    return info

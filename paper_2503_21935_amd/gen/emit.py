@@ -1,0 +1,469 @@
+"""Emit HIP source for one process from its evaluation plan.
+
+Output: a header with one struct per process holding
+  * compile-time sizes (particles, gluons, colour flows, helicities);
+  * ``amps<T>(ext, J)``: one helicity's straight-line program (currents,
+    top-line nodes, amplitudes, colour-flow accumulation into J);
+  * ``colour_sum<T>(J)``: J^dag N J with the integer numerators N of the
+    colour matrix (the caller divides by the common denominator);
+  * the static algorithmic flop count of one helicity (FMA = 2 flops,
+    division and square root = 1), used for roofline accounting.
+"""
+from __future__ import annotations
+
+import math
+
+from .colour import colour_matrix_exact, orderings
+from .diagrams import count_feynman_diagrams
+from .plan import Plan
+
+# Floating-point operations of each primitive in me_vertex.h (FMA counted as 2).
+FLOPS = dict(
+    dot_cc=30, dot_rc=14, vvv=150, vvvv=116, row_slash=64, slash_col=64, row_prop=58, prop_col=58,
+    scale_sp=24, row_col=30, fbar_gamma_f=72, vscale_c=24, vscale_r=8, vadd=8, jacc=2,
+    mom_add=4, msq=7, recip=1, crecip=6, eps=24, spinor=40,
+)
+
+
+def _coef_ops(c):
+    c = complex(c)
+    if abs(abs(c) - 1) > 1e-12 or (c.real != 0 and c.imag != 0):
+        raise ValueError(f"unexpected colour coefficient {c}")
+    if c == 1:
+        return "add"
+    if c == -1:
+        return "sub"
+    if c == 1j:
+        return "add_i"
+    return "sub_i"
+
+
+class GGEmitter:
+    """g g -> t tbar + (n-2) gluons."""
+
+    def __init__(self, name: str, n: int, merge: bool = True, cap: int = 8):
+        self.name = name
+        self.cap = cap
+        self.n = n
+        self.plan = Plan(n, merge)
+        self.perms = orderings(n)
+        self.kindex = {p: i for i, p in enumerate(self.perms)}
+        self.num, self.lcd = colour_matrix_exact(n)
+        self.lines = []
+        self.flops = 0
+
+    def w(self, s=""):
+        self.lines.append("    " + s)
+
+    # gluon current symbols
+    def cur(self, cid):
+        c = self.plan.currents[cid]
+        if c.is_leaf:
+            return f"x.eps[{next(iter(c.leaves))}]"
+        return f"w{cid}"
+
+    # ------------------------------------------------------------------
+    # momenta
+    # ------------------------------------------------------------------
+    def qexpr(self, leaves):
+        """Incoming-flow momentum of a gluon subset, as an expression."""
+        terms = [f"q{a}" for a in sorted(leaves)]
+        self.flops += FLOPS["mom_add"] * (len(terms) - 1)
+        return terms[0] if len(terms) == 1 else "(" + " + ".join(terms) + ")"
+
+    def prop_momentum(self, S):
+        """Momentum of the top line after the gluons S (counted from the top end):
+        p3 - Q_S, or equivalently Q_rest - p4.  The form that sums fewer of the
+        two beam momenta (|p| = sqrt(s)/2) is used, which rounds less."""
+        rest = set(range(self.n)) - set(S)
+        nin = lambda X: sum(1 for a in X if a < 2)
+        if S and (not rest or nin(S) <= nin(rest)):
+            return f"p3 - {self.qexpr(S)}"
+        if not S:
+            return "p3"
+        return f"{self.qexpr(rest)} - p4"
+
+    def leaves_of(self, cid):
+        return self.plan.currents[cid].leaves
+
+    # ------------------------------------------------------------------
+    # node symbols: every (re)computation of a node gets its own name
+    # ------------------------------------------------------------------
+    def sym(self, node):
+        kind = node[0]
+        if kind == "c":
+            c = self.plan.currents[node[1]]
+            if c.is_leaf:
+                return f"x.eps[{next(iter(c.leaves))}]"
+        if kind == "L" and node[1] == ():
+            return "x.ubar3"
+        if kind == "R" and node[1] == ():
+            return "x.v4"
+        return self.names[node]
+
+    def cur(self, cid):
+        return "opq(" + self.sym(("c", cid)) + ")"
+
+    def osym(self, node):
+        return "opq(" + self.sym(node) + ")"
+
+    def deps(self, node):
+        kind = node[0]
+        if kind == "c":
+            c = self.plan.currents[node[1]]
+            out = []
+            for t in c.terms:
+                for k in t[2]:
+                    if not self.plan.currents[k].is_leaf:
+                        out.append(("c", k))
+            return list(dict.fromkeys(out))
+        if kind == "L":
+            key = node[1]
+            out = []
+            if len(key) > 1:
+                out.append(("L", key[:-1]))
+            if not self.plan.currents[key[-1]].is_leaf:
+                out.append(("c", key[-1]))
+            return out
+        if kind == "R":
+            key = node[1]
+            out = []
+            if len(key) > 1:
+                out.append(("R", key[1:]))
+            if not self.plan.currents[key[0]].is_leaf:
+                out.append(("c", key[0]))
+            return out
+        if kind == "vt":
+            return []
+        amp = self.plan.amps[node[1]]
+        if amp["kind"] == "root":
+            out = [("vt",)]
+            for t in amp["terms"]:
+                for k in t[2]:
+                    if not self.plan.currents[k].is_leaf:
+                        out.append(("c", k))
+            return list(dict.fromkeys(out))
+        out = []
+        if amp["L"]:
+            out.append(("L", amp["L"]))
+        if not self.plan.currents[amp["W"]].is_leaf:
+            out.append(("c", amp["W"]))
+        if amp["R"]:
+            out.append(("R", amp["R"]))
+        return out
+
+    def closure(self, node, acc=None):
+        if acc is None:
+            acc = set()
+        for d in self.deps(node):
+            if d not in acc:
+                acc.add(d)
+                self.closure(d, acc)
+        return acc
+
+    def schedule(self, cap):
+        """Order the amplitudes so that consecutive ones share wavefunctions, then
+        walk them keeping at most ``cap`` wavefunctions alive: a node with no
+        further use is dropped; if room is needed, the live node whose next use
+        is furthest away is dropped and recomputed when needed again."""
+        amps = [("a", i) for i in range(len(self.plan.amps))]
+        clos = {a: self.closure(a) for a in amps}
+        # phase 1: greedy order (no eviction)
+        done = set()
+        order = []
+        remaining = list(amps)
+        while remaining:
+            best = min(remaining, key=lambda a: (len(clos[a] - done), a[1]))
+            order.append(best)
+            done |= clos[best]
+            remaining.remove(best)
+        # phase 2: simulate with a live-set cap
+        uses = {}
+        for t, a in enumerate(order):
+            for d in clos[a]:
+                uses.setdefault(d, []).append(t)
+        live = set()
+        ops = []
+        self.peak_live = 0
+
+        def next_use(node, t):
+            for u in uses.get(node, []):
+                if u >= t:
+                    return u
+            return 1 << 30
+
+        def materialise(node, t, protect):
+            if node in live:
+                return
+            for d in self.deps(node):
+                materialise(d, t, protect)
+            while len(live) >= cap:
+                cands = [v for v in live if v not in protect]
+                if not cands:
+                    break
+                victim = max(cands, key=lambda v: next_use(v, t))
+                live.discard(victim)
+            ops.append(node)
+            live.add(node)
+            self.peak_live = max(self.peak_live, len(live))
+
+        for t, a in enumerate(order):
+            protect = clos[a]
+            for d in self.deps(a):
+                materialise(d, t, protect)
+            ops.append(a)
+            for v in list(live):
+                if next_use(v, t + 1) >= (1 << 30):
+                    live.discard(v)
+        return ops
+
+    # ------------------------------------------------------------------
+    # emission of one node
+    # ------------------------------------------------------------------
+    def new_name(self, node):
+        self.counter += 1
+        kind = node[0]
+        prefix = {"c": "w", "L": "l", "R": "r", "vt": "vt"}[kind]
+        nm = f"{prefix}{self.counter}"
+        self.names[node] = nm
+        return nm
+
+    def vertex_sum(self, terms, indent="    "):
+        """Emit s3 = sum c vvv(..), s4 = sum c vvvv(..); return the names used."""
+        s3 = [t for t in terms if t[1] == "v3"]
+        s4 = [t for t in terms if t[1] == "v4"]
+        parts = []
+        for nm, group in (("s3", s3), ("s4", s4)):
+            if not group:
+                continue
+            parts.append(nm)
+            first = True
+            for coef, kind, kids, ch in group:
+                if kind == "v3":
+                    a, b = kids
+                    expr = (f"vvv({self.cur(a)}, {self.qexpr(self.leaves_of(a))}, "
+                            f"{self.cur(b)}, {self.qexpr(self.leaves_of(b))})")
+                    self.flops += FLOPS["vvv"]
+                else:
+                    a, b, cc = kids
+                    expr = f"vvvv({self.cur(a)}, {self.cur(b)}, {self.cur(cc)}, {ch})"
+                    self.flops += FLOPS["vvvv"]
+                op = _coef_ops(coef)
+                if first:
+                    pre = {"add": "", "sub": "vscale(T(-1), ", "add_i": "vscale(mk(T(0), T(1)), ",
+                           "sub_i": "vscale(mk(T(0), T(-1)), "}[op]
+                    post = "" if op == "add" else ")"
+                    self.w(f"{indent}vec4<T> {nm} = {pre}{expr}{post};")
+                    first = False
+                else:
+                    fn = {"add": "vadd", "sub": "vsub", "add_i": "vadd_i", "sub_i": "vsub_i"}[op]
+                    self.w(f"{indent}{fn}({nm}, {expr});")
+                    self.flops += FLOPS["vadd"]
+        return parts
+
+    def emit_node(self, node):
+        kind = node[0]
+        # New SSA names for the momenta before every node: helicity-independent
+        # subexpressions (subset sums, propagator denominators) are recomputed
+        # where needed instead of being merged into long-lived registers.
+        self.w("fence(" + ", ".join(self.mom_names) + ");")
+        if kind == "c":
+            c = self.plan.currents[node[1]]
+            self.w(f"// gluon current over {sorted(c.leaves)} ({len(c.terms)} vertex terms)")
+            self.w("vec4<T> " + self.new_name(node) + ";")
+            nm = self.names[node]
+            self.w("{")
+            self.w(f"    const T iq2 = T(1) / msq({self.qexpr(c.leaves)});")
+            self.flops += FLOPS["msq"] + FLOPS["recip"]
+            parts = self.vertex_sum(c.terms)
+            # W = (-i g / Q^2) s3 + (-g^2 / Q^2) s4
+            if "s3" in parts and "s4" in parts:
+                self.w(f"    {nm} = vscale(mk(T(0), -x.g * iq2), s3);")
+                self.w(f"    vacc({nm}, mk(-x.g * x.g * iq2, T(0)), s4);")
+                self.flops += FLOPS["vscale_c"] + 32
+            elif "s3" in parts:
+                self.w(f"    {nm} = vscale(mk(T(0), -x.g * iq2), s3);")
+                self.flops += FLOPS["vscale_c"]
+            else:
+                self.w(f"    {nm} = vscale(-x.g * x.g * iq2, s4);")
+                self.flops += FLOPS["vscale_r"]
+            self.w("}")
+        elif kind == "L":
+            key = node[1]
+            prev, last = key[:-1], key[-1]
+            S = set()
+            for b in key:
+                S |= self.leaves_of(b)
+            src = self.osym(("L", prev))
+            nm = self.new_name(node)
+            # L' = L (i g gamma.W) i (P + m)/D  with P = p3 - Q_union
+            self.w(f"spinor<T> {nm};")
+            self.w("{")
+            self.w(f"    const mom4<T> P = {self.prop_momentum(S)};")
+            self.w("    const cx<T> f = x.g * crecip(msq(P) - x.m * x.m, x.mw);  // g/D")
+            self.w(f"    {nm} = scale(-f, row_prop(row_slash({src}, {self.cur(last)}), P, x.m));")
+            self.w("}")
+            self.flops += FLOPS["mom_add"] + FLOPS["msq"] + 2 + FLOPS["crecip"] + 2 + FLOPS["row_slash"] + \
+                FLOPS["row_prop"] + FLOPS["scale_sp"]
+        elif kind == "R":
+            key = node[1]
+            first, rest = key[0], key[1:]
+            S = set()
+            for b in key:
+                S |= self.leaves_of(b)
+            src = self.osym(("R", rest))
+            nm = self.new_name(node)
+            # R' = i (P + m)/D (i g gamma.W) R  with P = Q_union - p4
+            self.w(f"spinor<T> {nm};")
+            self.w("{")
+            self.w(f"    const mom4<T> P = {self.prop_momentum(set(range(self.n)) - S)};")
+            self.w("    const cx<T> f = x.g * crecip(msq(P) - x.m * x.m, x.mw);  // g/D")
+            self.w(f"    {nm} = scale(-f, prop_col(P, x.m, slash_col({self.cur(first)}, {src})));")
+            self.w("}")
+            self.flops += FLOPS["mom_add"] + FLOPS["msq"] + 2 + FLOPS["crecip"] + 2 + FLOPS["slash_col"] + \
+                FLOPS["prop_col"] + FLOPS["scale_sp"]
+        elif kind == "vt":
+            nm = self.new_name(node)
+            self.w("// t tbar current (g/Q_T^2) ubar gamma v, Q_T = p3 + p4")
+            self.w(f"const vec4<T> {nm} = vscale(x.g / msq(p3 + p4), fbar_gamma_f(opq(x.ubar3), opq(x.v4)));")
+            self.flops += FLOPS["mom_add"] + FLOPS["msq"] + FLOPS["recip"] + 1 + FLOPS["fbar_gamma_f"] + \
+                FLOPS["vscale_r"]
+        else:
+            self.emit_amp(node[1])
+
+    def emit_jacc(self, amp_sym, colour):
+        for order, c in sorted(colour.items()):
+            k = self.kindex[order]
+            op = _coef_ops(c)
+            if op == "add":
+                self.w(f"    J[{k}] += {amp_sym};")
+            elif op == "sub":
+                self.w(f"    J[{k}] -= {amp_sym};")
+            elif op == "add_i":
+                self.w(f"    J[{k}] += times_i({amp_sym});")
+            else:
+                self.w(f"    J[{k}] -= times_i({amp_sym});")
+            self.flops += FLOPS["jacc"]
+
+    def emit_amp(self, idx):
+        amp = self.plan.amps[idx]
+        self.w("{")
+        if amp["kind"] == "root":
+            self.w(f"    // single-tree diagrams, colour structure {idx}")
+            parts = self.vertex_sum(amp["terms"])
+            vt = self.osym(("vt",))
+            # A = g dot(s3, VT) + (-i g^2) dot(s4, VT); VT carries g/Q_T^2
+            if "s3" in parts and "s4" in parts:
+                self.w(f"    const cx<T> a = x.g * dot(s3, {vt}) + times_mi(x.g * x.g * dot(s4, {vt}));")
+                self.flops += 2 * FLOPS["dot_cc"] + 6
+            elif "s3" in parts:
+                self.w(f"    const cx<T> a = x.g * dot(s3, {vt});")
+                self.flops += FLOPS["dot_cc"] + 2
+            else:
+                self.w(f"    const cx<T> a = times_mi(x.g * x.g * dot(s4, {vt}));")
+                self.flops += FLOPS["dot_cc"] + 3
+        else:
+            L = self.osym(("L", amp["L"]))
+            R = self.osym(("R", amp["R"]))
+            self.w(f"    const cx<T> a = times_i(x.g * row_col(row_slash({L}, {self.cur(amp['W'])}), {R}));")
+            self.flops += FLOPS["row_slash"] + FLOPS["row_col"] + 2
+        self.emit_jacc("a", amp["colour"])
+        self.w("}")
+
+    def emit_amps(self):
+        self.names = {}
+        self.counter = 0
+        self.mom_names = [f"q{a}" for a in range(self.n)] + ["p3", "p4"]
+        for a in range(self.n):
+            self.w(f"mom4<T> q{a} = x.q[{a}];")
+        self.w("mom4<T> p3 = x.p3, p4 = x.p4;")
+        ops = self.schedule(self.cap)
+        self.n_ops = len(ops)
+        for node in ops:
+            self.emit_node(node)
+
+    def emit_colour(self):
+        N = self.num
+        ncol = len(N)
+        out = []
+        out.append("    T acc = T(0);")
+        for k in range(ncol):
+            terms_r = [f"T({N[k][k]}) * J[{k}].r"]
+            terms_i = [f"T({N[k][k]}) * J[{k}].i"]
+            zr = f"T({N[k][k]}) * J[{k}].r"
+            zi = f"T({N[k][k]}) * J[{k}].i"
+            for l in range(k + 1, ncol):
+                if N[k][l] == 0:
+                    continue
+                zr = f"fma(T({2 * N[k][l]}), J[{l}].r, {zr})"
+                zi = f"fma(T({2 * N[k][l]}), J[{l}].i, {zi})"
+            out.append(f"    {{ const T zr = {zr};")
+            out.append(f"      const T zi = {zi};")
+            out.append(f"      acc = fma(J[{k}].r, zr, fma(J[{k}].i, zi, acc)); }}")
+        out.append("    return acc;")
+        return out
+
+    def colour_flops(self):
+        ncol = len(self.num)
+        return 2 * ncol * ncol + 6 * ncol
+
+    def algorithmic_flops(self):
+        """Flops of one helicity with every wavefunction computed exactly once."""
+        keep = (self.lines, self.flops, self.cap)
+        self.lines, self.flops, self.cap = [], 0, 1 << 30
+        self.emit_amps()
+        f = self.flops
+        self.lines, self.flops, self.cap = keep
+        return f
+
+    def render(self) -> str:
+        alg = self.algorithmic_flops()
+        self.lines = []
+        self.flops = 0
+        self.emit_amps()
+        body = self.lines
+        executed_flops = self.flops
+        amp_flops = alg
+        ext_flops = FLOPS["eps"] * self.n + 2 * FLOPS["spinor"]
+        n = self.n
+        nc = len(self.perms)
+        st = self.plan.stats()
+        h = []
+        h.append(f"// Generated by paper_2503_21935_amd.gen for {self.name}: g g -> t tbar + {n - 2} g.")
+        h.append(f"// {st['currents']} gluon currents ({st['current_terms']} vertex terms), "
+                 f"{st['L_nodes']}+{st['R_nodes']} top-line nodes, {st['amplitudes']} amplitudes, "
+                 f"{st['colour_pairs']} colour-flow contributions per helicity; merge={self.plan.merge}.")
+        h.append("#pragma once")
+        h.append('#include "me_vertex.h"')
+        h.append('#include "me_process.h"')
+        h.append("")
+        h.append(f"struct proc_{self.name} {{")
+        h.append(f"    static constexpr int npart = {n + 2};")
+        h.append(f"    static constexpr int ngluon = {n};")
+        h.append(f"    static constexpr int ncol = {nc};")
+        h.append(f"    static constexpr int nhel = {1 << (n + 2)};")
+        h.append(f"    static constexpr int lcd = {self.lcd};")
+        h.append(f"    static constexpr int identical = {math.factorial(n - 2)};")
+        h.append(f"    static constexpr double flops_amp = {amp_flops + ext_flops};  // per helicity, excl. colour")
+        h.append(f"    static constexpr double flops_executed = {executed_flops + ext_flops};  // incl. recomputation")
+        h.append(f"    static constexpr double flops_colour = {self.colour_flops()};  // per helicity")
+        h.append(f"    static constexpr int n_amplitudes = {st['amplitudes']};")
+        h.append(f"    static constexpr int ndiag = {count_feynman_diagrams(n)};")
+        h.append("")
+        h.append("    template <typename T>")
+        h.append("    static MEV void amps(const gg_ext<T, " + str(n) + ">& x, cx<T>* __restrict__ J) {")
+        h.extend(body)
+        h.append("    }")
+        h.append("")
+        h.append("    // J^dag N J with N = lcd * C (integer numerators, symmetric)")
+        h.append("    template <typename T>")
+        h.append("    static MEV T colour_sum(const cx<T>* __restrict__ J) {")
+        h.extend(self.emit_colour())
+        h.append("    }")
+        h.append("")
+        h.append(f"    static constexpr int colour_num[{nc}][{nc}] = {{")
+        for row in self.num:
+            h.append("        {" + ", ".join(str(v) for v in row) + "},")
+        h.append("    };")
+        h.append("};")
+        return "\n".join(h) + "\n"
