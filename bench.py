@@ -4,14 +4,19 @@ Workload: g g -> t tbar g g at sqrt(s) = 13 TeV, 2^20 seeded RAMBO points
 (seed 2), float64 momenta resident in HBM.  One step = one evaluation of
 |M|^2 for every point (all helicities, diagrams and colour sums).
 
-Prints one JSON line: MEs/s, the roofline of the dominant kernel (measured
-with HIP events on the launch stream) and the CPU oracle timed on a bounded
-sample of the same workload.
+Prints one JSON line.  `value` is the float64 form's MEs/s; the mixed form
+(float32 amplitudes + float16 hi/lo MFMA colour sum + float64 rerun of flagged
+events) and the surrogate form (network trained on exact labels, two-stage
+unweighting) are reported under "forms".  `roofline` is the dominant float64
+kernel, timed with HIP events on its launch stream; `cpu_baseline` is the CPU
+oracle on a bounded sample of the same points.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -19,7 +24,207 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16_mfma": 2500.0}  # MI355X, TFLOP/s (dense)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, stream):
+    """Average kernel-side time of fn() over `steps` calls (HIP events on `stream`) and wall time."""
+    import torch
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - w0) / steps
+    return e0.elapsed_time(e1) / steps * 1e-3, wall
+
+
+def kernel_sources_digest(process):
+    """Digest of the sources that make up the float64 kernel of `process`."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2503_21935_amd", "csrc")
+    for f in ("me_vertex.h", "me_process.h", "me_kernels.h", "me_launch.h", os.path.join("gen", f"proc_{process}.h")):
+        p = os.path.join(csrc, f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(process, kernel):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernel's sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec or rec.get("sources") != kernel_sources_digest(process):
+        return None
+    return rec["fetch_kib"] * rec["fetch_factor"] * 1024 + rec["write_kib"] * rec["write_factor"] * 1024
+
+
+def bench_fp64(m, mom, out, args, stream):
+    for _ in range(args.warmup):
+        m.eval(mom, out=out, stream=stream)
+    return timed(lambda: m.eval(mom, out=out, stream=stream), args.steps, stream)
+
+
+def bench_mixed(me, m, mom, mom_np, args, stream):
+    import numpy as np
+    import torch
+
+    import oracle
+
+    m.set_precision(me.ME_MIXED, args.tol)
+    out = torch.empty(mom.shape[0], dtype=torch.float64, device=mom.device)
+    for _ in range(args.warmup):
+        m.eval(mom, out=out, stream=stream)
+    k_s, wall = timed(lambda: m.eval(mom, out=out, stream=stream), args.steps, stream)
+    nfb = m.fallback_count()
+    res = out.cpu().numpy()
+    raw, est, flag = m.eval_mixed_diag(mom, stream=stream)
+    diag_s, _ = timed(lambda: m.eval_mixed_diag(mom, stream=stream), 3, stream)
+    torch.cuda.synchronize()
+    raw = raw.cpu().numpy()
+    idx = np.sort(np.random.default_rng(3).choice(len(res), args.check, replace=False))
+    ref = oracle.me2(args.process, mom_np[idx])
+    rel = np.abs(res[idx] / ref - 1)
+    rel_raw = np.abs(raw[idx] / ref - 1)
+    m.set_precision(me.ME_FP64, args.tol)
+    n = mom.shape[0]
+    return {
+        "MEs_per_s": n / wall, "ms_per_step": wall * 1e3, "tolerance": args.tol,
+        "fallback_fraction": nfb / n,
+        "mixed_kernel_ms_without_rerun": diag_s * 1e3,
+        "max_rel_err_vs_oracle": float(rel.max()),
+        "float32_form_rel_err": {"p50": float(np.median(rel_raw)), "p99.9": float(np.quantile(rel_raw, 0.999)),
+                                 "max": float(rel_raw.max())},
+        "checked_events": int(args.check),
+    }
+
+
+def bench_surrogate(me, args, stream):
+    import numpy as np
+    import torch
+
+    from inputs import gluon_cuts, process_points, uniforms
+
+    dev = torch.device("cuda:0")
+    proc = args.process
+    t0 = time.time()
+    mom_tr = process_points(proc, args.n_train, 4, precise=False)
+    mom_tr = mom_tr[gluon_cuts(mom_tr)]
+    log(f"surrogate: {len(mom_tr)} training points after cuts ({time.time() - t0:.1f}s)")
+    ctx = me.MatrixElement(proc)
+    mt = torch.from_numpy(mom_tr).to(dev)
+    del mom_tr
+    lab = ctx.eval(mt)  # labels from the exact float64 kernel
+    x = me.features(mt)
+    del mt
+    lnl = torch.log(lab)
+    mu, sig = float(lnl.mean()), float(lnl.std())
+    t = ((lnl - mu) / sig).float()
+    n = t.shape[0]
+    n_val = n // 10
+    n_fit = (n - n_val) // args.batch * args.batch
+    net = me.Surrogate(seed=1004)
+    rng = np.random.default_rng(7)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    steps_per_epoch = n_fit // args.batch
+    total = steps_per_epoch * args.epochs
+    torch.cuda.synchronize()
+    tt0 = time.perf_counter()
+    step = 0
+    for ep in range(args.epochs):
+        perm = torch.from_numpy(rng.permutation(n_fit).astype(np.int32) + n_val).to(dev)
+        for b in range(steps_per_epoch):
+            lr = 0.5 * args.lr * (1 + math.cos(math.pi * step / total))
+            net.train_step(x, t, perm[b * args.batch:(b + 1) * args.batch], lr, loss, stream)
+            step += 1
+        log(f"surrogate: epoch {ep + 1}/{args.epochs}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - tt0
+    yv = net.forward(x[:n_val])
+    val_mse = float(torch.mean((yv - t[:n_val]) ** 2))
+    yall = torch.empty(n, dtype=torch.float32, device=dev)
+    inf_s, _ = timed(lambda: me.mlp_forward(net.h, x, n, yall, stream), 3, stream)
+    del x, t, lab, lnl, yall
+    # s_max and r_max from an independent calibration sample (seed 6)
+    mom_c, w_c = process_points(proc, args.n_calib, 6, return_weight=True, precise=False)
+    w_c = w_c * gluon_cuts(mom_c)
+    mc = torch.from_numpy(mom_c).to(dev)
+    wc_t = torch.from_numpy(w_c).to(dev)
+    yc = net.forward(me.features(mc)).double()
+    s_c = torch.exp(sig * yc + mu) * wc_t
+    wex_c = ctx.eval(mc) * wc_t
+    # Reduced maxima (a quantile of the calibration sample): flat phase space puts
+    # single points many orders above the bulk; points above a maximum are kept
+    # with weight > 1, so both unweightings stay unbiased.
+    pos = s_c > 0
+    q = args.max_quantile
+    s_max = float(torch.quantile(s_c[pos].float(), q))
+    r_max = float(torch.quantile((wex_c[pos] / s_c[pos]).float(), q))
+    w_max = float(torch.quantile(wex_c[pos].float(), q))
+    del mc, mom_c
+    # unweighting sample (seed 5): two-stage, then exact-only on the same points
+    mom_u, w_u = process_points(proc, args.n_unweight, 5, return_weight=True, precise=False)
+    w_u = w_u * gluon_cuts(mom_u)
+    nu = len(mom_u)
+    u = uniforms(nu, 2, 55)
+    mu_t = torch.from_numpy(mom_u).to(dev)
+    wu_t = torch.from_numpy(w_u).to(dev)
+    uu_t = torch.from_numpy(u).to(dev)
+    del mom_u
+    out_idx = torch.empty(nu, dtype=torch.int32, device=dev)
+    out_w = torch.empty(nu, dtype=torch.float64, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int32, device=dev)
+
+    def two_stage():
+        me.unweight_two_stage(ctx.ctx, net.h, mu_t, wu_t, nu, uu_t, mu, sig, s_max, r_max, out_idx, out_w, cnt,
+                              stream)
+
+    two_stage()
+    _, two_s = timed(two_stage, 1, stream)
+    n1, n2 = [int(v) for v in cnt.cpu()]
+    wsel = out_w[:n2]
+    neff2 = float(wsel.sum() ** 2 / (wsel ** 2).sum()) if n2 else 0.0
+    me2_all = torch.empty(nu, dtype=torch.float64, device=dev)
+    one = {}
+
+    def exact_only():
+        ctx.eval(mu_t, out=me2_all, stream=stream)
+        wex = me2_all * wu_t
+        one["acc"] = uu_t[:, 0] < torch.clamp(wex / w_max, max=1.0)
+        one["wt"] = torch.clamp(wex / w_max, min=1.0)
+
+    exact_only()
+    _, one_s = timed(exact_only, 1, stream)
+    sel1 = one["wt"][one["acc"]]
+    neff1 = float(sel1.sum() ** 2 / (sel1 ** 2).sum()) if sel1.numel() else 0.0
+    mlp_flops = 2 * (24 * 256 + 3 * 256 * 256 + 256)
+    gain = (one_s / max(neff1, 1e-30)) / (two_s / max(neff2, 1e-30))
+    ctx.close()
+    net.close()
+    return {
+        "train_samples_per_s": total * args.batch / train_s, "train_epochs": args.epochs,
+        "train_points": int(n_fit), "val_mse_standardised_log_me2": val_mse,
+        "inference_samples_per_s": n / inf_s,
+        "inference_tflops": mlp_flops * n / inf_s / 1e12,
+        "inference_frac_of_bf16_mfma_peak": mlp_flops * n / inf_s / 1e12 / PEAK["bf16_mfma"],
+        "unweighting_points": nu, "unweighting_points_per_s": nu / two_s,
+        "stage1_kept": n1, "exact_calls_per_point": n1 / nu, "accepted": n2, "n_eff": neff2,
+        "exact_only": {"points_per_s": nu / one_s, "accepted": int(one["acc"].sum()), "n_eff": neff1},
+        "gain_cost_per_effective_event": gain,
+        "s_max": s_max, "r_max": r_max, "w_max": w_max, "max_quantile": args.max_quantile,
+        "cuts": "gluon pT > 20 GeV, |eta| < 5, Delta R > 0.4",
+    }
 
 
 def main():
@@ -30,12 +235,27 @@ def main():
     ap.add_argument("--nevt", type=int, default=1 << 20)
     ap.add_argument("--process", default="gg_ttgg")
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 13, help="events for the CPU oracle baseline")
+    ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
+    ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
+    ap.add_argument("--forms", default="fp64,mixed,surrogate")
+    ap.add_argument("--n-train", type=int, default=1 << 22)
+    ap.add_argument("--n-calib", type=int, default=1 << 20)
+    ap.add_argument("--n-unweight", type=int, default=1 << 22)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--max-quantile", type=float, default=0.999,
+                    help="unweighting maxima: this quantile of the calibration sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device-to-device copy of this many MiB (a reference kernel of "
+                         "known traffic for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    forms = set(args.forms.split(","))
 
     import numpy as np
     import torch
@@ -45,45 +265,41 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nb} bytes read, {nb} bytes written")
+        del a, b
     t0 = time.time()
     mom_np = process_points(args.process, args.nevt, args.seed)
-    print(f"[bench] generated {args.nevt} points in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"generated {args.nevt} points in {time.time() - t0:.1f}s")
     mom = torch.from_numpy(mom_np).to(dev)
     out = torch.empty(args.nevt, dtype=torch.float64, device=dev)
     m = me.MatrixElement(args.process)
     info = m.info()
-    stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        m.eval(mom, out=out, stream=stream)
-    torch.cuda.synchronize()
-
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        m.eval(mom, out=out, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    kernel_ms = ev0.elapsed_time(ev1) / args.steps  # one launch per step
-    ms_per_step = wall * 1e3 / args.steps
-    value = args.nevt / (ms_per_step * 1e-3)
-
-    flops_evt = info["flops_per_event"]
-    achieved = flops_evt * args.nevt / (kernel_ms * 1e-3) / 1e12
+    k_s, wall = bench_fp64(m, mom, out, args, stream)
     res = out.cpu().numpy()
     assert np.all(np.isfinite(res)), "non-finite results"
+    value = args.nevt / wall
+    flops_evt = info["flops_per_event"]
+    achieved = flops_evt * args.nevt / k_s / 1e12
+    kernel = f"k_me_gg<proc_{args.process}>"
+    traffic = traffic_from_profile(args.process, kernel)
+    log(f"fp64: {value:.3e} MEs/s, kernel {k_s * 1e3:.2f} ms")
 
     line = {
-        "metric": "matrix elements/sec, gg->ttgg 1 GPU (FP64 exact kernel)",
+        "metric": "matrix elements/sec, gg->ttgg 1 GPU: FP64 (value) vs mixed vs surrogate (forms)",
         "value": value,
         "unit": "MEs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -93,10 +309,19 @@ def main():
                                f"{info['nhel_good']} helicities, {info['ndiag']} diagrams, "
                                f"{info['ncol']}x{info['ncol']} colour matrix",
                    "nevt": args.nevt, "parallelism": "single GPU, one event per lane"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_event": flops_evt, "kernel_ms": kernel_ms},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp64"], "traffic": traffic,
+                     "kernel": kernel, "flops_per_event": flops_evt, "kernel_ms": k_s * 1e3},
+        "forms": {"fp64": {"MEs_per_s": value, "ms_per_step": wall * 1e3}},
     }
+    if "mixed" in forms:
+        line["forms"]["mixed"] = bench_mixed(me, m, mom, mom_np, args, stream)
+        log(f"mixed: {line['forms']['mixed']['MEs_per_s']:.3e} MEs/s")
+    m.close()
+    if "surrogate" in forms:
+        del mom
+        line["forms"]["surrogate"] = bench_surrogate(me, args, stream)
+        log(f"surrogate: {line['forms']['surrogate']}")
 
     if not args.no_cpu:
         import oracle
@@ -110,8 +335,7 @@ def main():
         line["cpu_baseline"] = {"value": n / cpu_s, "unit": "MEs/s", "cores": threads, "kind": "oracle",
                                 "sample": f"first {n} of the {args.nevt} points, float64 oracle "
                                           f"(colour-ordered Berends-Giele), {cpu_s:.1f} s"}
-        line["max_rel_dev_vs_oracle_on_sample"] = float(rel.max())
-    m.close()
+        line["fp64_max_rel_dev_vs_oracle_on_sample"] = float(rel.max())
     print(json.dumps(line), flush=True)
 
 

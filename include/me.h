@@ -85,6 +85,39 @@ int me_init(const char *process, const double *couplings, int n_couplings, const
 int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, void *stream);
 
 /*
+ * me_set_precision -- choose the evaluation form of later me_eval calls.
+ * ME_FP64 (default): float64 throughout.
+ * ME_MIXED: float32 wavefunctions and amplitudes (momentum algebra and
+ *   propagator denominators in float64), colour sum as a float16 hi/lo GEMM on
+ *   the matrix cores with float32 accumulation, and an a-posteriori estimate of
+ *   each event's relative rounding error; every event whose estimate exceeds
+ *   rel_tol is recomputed in float64 on the same stream, so each returned
+ *   value is expected within rel_tol of the exact float64 result.  Processes
+ *   without a mixed form (e+e- -> mu+mu-) keep evaluating in float64.
+ *   Mixed evaluation keeps a flagged-event index list in the context; it grows
+ *   on the first call with a larger nevt (that call synchronises the device).
+ * Errors: ME_EINVAL (unknown mode, rel_tol <= 0 for ME_MIXED).
+ */
+int me_set_precision(me_ctx *ctx, int mode, double rel_tol);
+
+/*
+ * me_eval_mixed_diag -- the mixed form without the float64 rerun, for checks.
+ * out_me2:  device float64 [nevt], the float32-form result of every event.
+ * out_err:  device float32 [nevt], the estimated relative error.
+ * out_flag: device uint8 [nevt], 1 where out_err exceeds the context's
+ *           tolerance (the events me_eval would recompute in float64).
+ * Errors: ME_EINVAL, ME_ESTATE (process without a mixed form), ME_EDEVICE.
+ */
+int me_eval_mixed_diag(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, float *out_err,
+                       uint8_t *out_flag, void *stream);
+
+/*
+ * me_fallback_count -- number of events the last mixed me_eval recomputed in
+ * float64.  Synchronises the device.  0 before any mixed evaluation.
+ */
+int me_fallback_count(me_ctx *ctx, int64_t *count);
+
+/*
  * me_eval_helicities -- per-helicity contributions, for checks.
  * out_qhel: device pointer, float64 [nevt][nhel]; entry h receives
  *           J_h^dag C J_h (before averaging) for every helicity combination

@@ -1,0 +1,112 @@
+/*
+ * mlp.h -- C ABI of the surrogate network and two-stage unweighting in libme.so.
+ *
+ * The learned part of the build (not in the paper): a multilayer perceptron
+ * that approximates the standardised logarithm of |M|^2 from the momenta,
+ * trained on the GPU by the library's own BF16 forward and backward kernels
+ * (matrix-core GEMMs with FP32 accumulation, FP32 master weights, Adam), and
+ * used to drive a two-stage unweighting in which the exact matrix element is
+ * the second stage, so the unweighted sample stays unbiased.
+ *
+ * Network: n_in inputs -> depth hidden layers of `width` units with SiLU ->
+ * one output.  Flat FP32 parameter layout (host copies):
+ *   [W_1 (width x n_in, row-major [out][in]), b_1, W_2 (width x width), b_2, ...,
+ *    W_depth, b_depth, w_out (width), b_out]
+ * Loss: mean squared error.  Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8
+ * and bias correction.
+ *
+ * Conventions as in me.h: status codes (ME_* from me.h), device pointers owned
+ * by the caller, asynchronous on the given stream (NULL = default stream).
+ */
+#ifndef MLP_H
+#define MLP_H
+
+#include <stdint.h>
+
+#include "me.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct me_mlp me_mlp;
+
+/*
+ * mlp_create -- allocate a network on the current device and initialise it:
+ * weights uniform in +-sqrt(6 / fan_in) (He-uniform), biases 0, from a
+ * splitmix64 stream keyed by seed; Adam moments 0, step 0.
+ * Constraints: 1 <= n_in <= 32, width a multiple of 64 (<= 1024), depth >= 1.
+ * Errors: ME_EINVAL, ME_ENOMEM, ME_EDEVICE.
+ */
+int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp **out);
+
+/* mlp_n_params -- number of FP32 parameters. */
+int mlp_n_params(const me_mlp *mlp, int64_t *n);
+
+/* mlp_get_params / mlp_set_params -- copy the FP32 master parameters to / from
+ * a host array of n = mlp_n_params entries (flat layout above).  Both
+ * synchronise the device; set also refreshes the BF16 working copy. */
+int mlp_get_params(me_mlp *mlp, float *host, int64_t n);
+int mlp_set_params(me_mlp *mlp, const float *host, int64_t n);
+
+/*
+ * mlp_forward -- y[i] = network(x[i]) for i < n.
+ * x: device float32 [n][n_in]; y: device float32 [n].  BF16 operands, FP32
+ * accumulation, FP32 bias and activation.  Works in chunks; any n >= 0.
+ */
+int mlp_forward(me_mlp *mlp, const float *x, int64_t n, float *y, void *stream);
+
+/*
+ * mlp_train_step -- one Adam step on the mini-batch {x[idx[j]], t[idx[j]]},
+ * j < n (idx == NULL: the first n rows).
+ * x: device float32 [*][n_in]; t: device float32 targets; idx: device int32 [n].
+ * n: batch size, a positive multiple of 64.  lr: learning rate of this step.
+ * loss_dev: device float32 [1] (may be NULL), receives the batch mean squared
+ * error before the update.
+ */
+int mlp_train_step(me_mlp *mlp, const float *x, const float *t, const int32_t *idx, int64_t n, float lr,
+                   float *loss_dev, void *stream);
+
+/*
+ * mlp_backward -- gradient of the batch loss only (no update), for checks.
+ * grad_dev: device float32 [n_params] (flat layout); loss_dev as above.
+ */
+int mlp_backward(me_mlp *mlp, const float *x, const float *t, const int32_t *idx, int64_t n, float *grad_dev,
+                 float *loss_dev, void *stream);
+
+int mlp_free(me_mlp *mlp);
+
+/*
+ * me_features -- network inputs from momenta: x[i][4 p + c] = momenta[i][p][c]
+ * / sqrt(s_i) as float32, with s_i = (p_0 + p_1)^2 of the incoming partons
+ * (the points are taken in the partonic centre-of-mass frame).
+ * momenta: device float64 [n][npart][4]; x: device float32 [n][4 npart].
+ */
+int me_features(const double *momenta, int64_t n, int npart, float *x, void *stream);
+
+/*
+ * unweight_two_stage -- two-stage unweighting of n points (Danziger, Janssen,
+ * Schumann, Siegert 2022).  For point i with phase-space weight w_ps[i]:
+ *   surrogate weight  s_i = exp(y_sigma * y_i + y_mu) * w_ps[i]   (y from the network),
+ *   stage 1: accept if u[i][0] < min(1, s_i / s_max);
+ *   exact weight w_i = |M|^2_i * w_ps[i] (me_eval of ctx, float64) for stage-1
+ *   survivors only;
+ *   stage 2: accept if u[i][1] < min(1, (w_i / s_i) / r_max);
+ *   output weight max(1, s_i/s_max) * max(1, (w_i/s_i)/r_max).
+ * momenta: device float64 [n][npart][4]; w_ps: device float64 [n];
+ * uniforms: device float64 [n][2] in (0,1).
+ * out_idx: device int32 [n], indices of accepted points in increasing order of
+ * stage-1 survival (order not guaranteed); out_w: device float64 [n], their
+ * weights; out_count: device int32 [2] = {stage-1 survivors (= exact
+ * evaluations), accepted}.  Scratch grows on the first call with a larger n
+ * (synchronises the device).  Errors: ME_EINVAL, ME_EDEVICE, ME_ENOMEM.
+ */
+int unweight_two_stage(me_ctx *ctx, me_mlp *mlp, const double *momenta, const double *w_ps, int64_t n,
+                       const double *uniforms, double y_mu, double y_sigma, double s_max, double r_max,
+                       int32_t *out_idx, double *out_w, int32_t *out_count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLP_H */

@@ -41,11 +41,11 @@ def uniforms(n: int, k: int, seed: int) -> np.ndarray:
 LD = np.longdouble
 
 
-def _massless(n_evt: int, n_fin: int, roots: float, g: np.random.Generator) -> np.ndarray:
+def _massless(n_evt: int, n_fin: int, roots: float, g: np.random.Generator, LD=LD) -> np.ndarray:
     """Flat massless n-body momenta at energy ``roots`` (RAMBO, Sec. 2 of KSE).
 
-    Computed in x87 extended precision so that, once rounded to float64, the
-    points are on shell and balance momentum to float64 rounding."""
+    Computed in x87 extended precision by default so that, once rounded to
+    float64, the points are on shell and balance momentum to float64 rounding."""
     r = g.random((n_evt, n_fin, 4)).astype(LD)
     c = 2.0 * r[..., 0] - 1.0
     phi = 2.0 * LD(math.pi) * r[..., 1]
@@ -78,17 +78,20 @@ def massless_volume(n_fin: int, s: float) -> float:
             * s ** (n_fin - 2) / (math.factorial(n_fin - 1) * math.factorial(n_fin - 2)))
 
 
-def rambo(n_evt: int, roots: float, masses, seed: int, return_weight: bool = False):
+def rambo(n_evt: int, roots: float, masses, seed: int, return_weight: bool = False, precise: bool = True):
     """``n_evt`` RAMBO points for 2 -> len(masses) at energy ``roots``.
 
     Returns momenta ``[n_evt][2 + n_fin][4]`` (and, if asked, the phase-space
     weight per point in the (2pi)^(4-3n) convention, so that the mean weight
-    estimates the phase-space volume).
+    estimates the phase-space volume).  ``precise=False`` works in float64
+    (about 5x faster; points then balance momentum to ~1e-13 relative only),
+    for large samples that feed training and unweighting.
     """
+    LD = np.longdouble if precise else np.float64
     masses = np.asarray(masses, dtype=np.float64)
     n_fin = masses.size
     g = rng(seed)
-    p = _massless(n_evt, n_fin, roots, g)
+    p = _massless(n_evt, n_fin, roots, g, LD)
     w0 = massless_volume(n_fin, roots * roots)
     if np.any(masses > 0.0):
         if masses.sum() >= roots:
@@ -103,7 +106,7 @@ def rambo(n_evt: int, roots: float, masses, seed: int, return_weight: bool = Fal
             df = (xi[:, None] * E0 * E0 / e).sum(axis=1)
             step = f / df
             xi = xi - step
-            if np.all(np.abs(step) <= 1e-19 * np.abs(xi)):
+            if np.all(np.abs(step) <= 4 * np.finfo(LD).eps * np.abs(xi)):
                 break
         k = np.empty_like(p)
         k[..., 1:] = xi[:, None, None] * p[..., 1:]
@@ -146,7 +149,27 @@ def process_masses(process: str):
     return PROCESS_KINEMATICS[process]["masses"]
 
 
-def process_points(process: str, n_evt: int, seed: int, return_weight: bool = False):
+def process_points(process: str, n_evt: int, seed: int, return_weight: bool = False, precise: bool = True):
     """Seeded RAMBO points for one of the named workloads."""
     k = PROCESS_KINEMATICS[process]
-    return rambo(n_evt, k["roots"], k["masses"], seed, return_weight=return_weight)
+    return rambo(n_evt, k["roots"], k["masses"], seed, return_weight=return_weight, precise=precise)
+
+
+def gluon_cuts(mom, pt_min: float = 20.0, eta_max: float = 5.0, dr_min: float = 0.4) -> np.ndarray:
+    """Generator-level cuts on the final-state gluons (particles 4, 5, ...):
+    p_T > pt_min, |eta| < eta_max, and Delta R > dr_min between gluon pairs.
+    Without them |M|^2 diverges in soft and collinear regions and unweighting is
+    ill-posed; points that fail get phase-space weight 0."""
+    g = np.asarray(mom)[:, 4:, :]
+    pt = np.hypot(g[..., 1], g[..., 2])
+    pabs = np.sqrt(pt ** 2 + g[..., 3] ** 2)
+    eta = np.arctanh(np.clip(g[..., 3] / np.maximum(pabs, 1e-300), -1 + 1e-15, 1 - 1e-15))
+    phi = np.arctan2(g[..., 2], g[..., 1])
+    ok = np.all((pt > pt_min) & (np.abs(eta) < eta_max), axis=1)
+    ng = g.shape[1]
+    for i in range(ng):
+        for j in range(i + 1, ng):
+            dphi = np.abs(phi[:, i] - phi[:, j])
+            dphi = np.minimum(dphi, 2 * np.pi - dphi)
+            ok &= np.hypot(eta[:, i] - eta[:, j], dphi) > dr_min
+    return ok

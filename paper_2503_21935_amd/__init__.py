@@ -49,6 +49,9 @@ def lib():
     L.me_eval_helicities.argtypes = [vp, vp, i64, vp, vp, vp]
     L.me_info.argtypes = [vp, ip, ip, ip, ip, ip, dp]
     L.me_good_helicities.argtypes = [vp, ip, ip]
+    L.me_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+    L.me_eval_mixed_diag.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    L.me_fallback_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.me_free.argtypes = [vp]
     L.me_strerror.argtypes = [ctypes.c_int]
     L.me_strerror.restype = ctypes.c_char_p
@@ -134,6 +137,23 @@ def me_good_helicities(ctx) -> list:
     return list(buf[:cnt.value])
 
 
+def me_set_precision(ctx, mode: int, rel_tol: float = 1e-5) -> None:
+    _check(lib().me_set_precision(ctx, int(mode), float(rel_tol)), "me_set_precision")
+
+
+def me_eval_mixed_diag(ctx, momenta, nevt: int, out_me2, out_err, out_flag, stream=None) -> None:
+    _check(lib().me_eval_mixed_diag(ctx, _dev_ptr(momenta, "float64", "momenta"), int(nevt),
+                                    _dev_ptr(out_me2, "float64", "out_me2"), _dev_ptr(out_err, "float32", "out_err"),
+                                    _dev_ptr(out_flag, "uint8", "out_flag"), _stream_handle(stream)),
+           "me_eval_mixed_diag")
+
+
+def me_fallback_count(ctx) -> int:
+    c = ctypes.c_int64()
+    _check(lib().me_fallback_count(ctx, ctypes.byref(c)), "me_fallback_count")
+    return c.value
+
+
 def me_free(ctx) -> None:
     _check(lib().me_free(ctx), "me_free")
 
@@ -185,6 +205,24 @@ class MatrixElement:
         me_eval_helicities(self.ctx, momenta, n, out, q, stream)
         return out, q
 
+    def set_precision(self, mode, rel_tol=1e-5):
+        me_set_precision(self.ctx, mode, rel_tol)
+
+    def eval_mixed_diag(self, momenta, stream=None):
+        """Mixed form without the float64 rerun: (me2, error estimate, flag)."""
+        import torch
+
+        self._check_mom(momenta)
+        n = momenta.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        err = torch.empty(n, dtype=torch.float32, device=momenta.device)
+        flag = torch.empty(n, dtype=torch.uint8, device=momenta.device)
+        me_eval_mixed_diag(self.ctx, momenta, n, out, err, flag, stream)
+        return out, err, flag
+
+    def fallback_count(self) -> int:
+        return me_fallback_count(self.ctx)
+
     def close(self):
         if self.ctx is not None:
             me_free(self.ctx)
@@ -201,3 +239,154 @@ class MatrixElement:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# --------------------------------------------------------------------------
+# Surrogate network and two-stage unweighting (include/mlp.h)
+# --------------------------------------------------------------------------
+
+def _mlp_sigs(L):
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    if getattr(L, "_mlp_ready", False):
+        return L
+    L.mlp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.mlp_n_params.argtypes = [vp, ctypes.POINTER(i64)]
+    L.mlp_get_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
+    L.mlp_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
+    L.mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    L.mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, vp]
+    L.mlp_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
+    L.mlp_free.argtypes = [vp]
+    L.me_features.argtypes = [vp, i64, ctypes.c_int, vp, vp]
+    L.unweight_two_stage.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, vp, vp, vp, vp]
+    L._mlp_ready = True
+    return L
+
+
+def _opt_ptr(t, dtype_name, what):
+    return None if t is None else _dev_ptr(t, dtype_name, what)
+
+
+def mlp_create(n_in=24, width=256, depth=4, seed=1004):
+    h = ctypes.c_void_p()
+    _check(_mlp_sigs(lib()).mlp_create(n_in, width, depth, seed, ctypes.byref(h)), "mlp_create")
+    return h
+
+
+def mlp_n_params(h) -> int:
+    n = ctypes.c_int64()
+    _check(_mlp_sigs(lib()).mlp_n_params(h, ctypes.byref(n)), "mlp_n_params")
+    return n.value
+
+
+def mlp_get_params(h):
+    import numpy as np
+
+    n = mlp_n_params(h)
+    out = np.empty(n, dtype=np.float32)
+    _check(lib().mlp_get_params(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n), "mlp_get_params")
+    return out
+
+
+def mlp_set_params(h, params) -> None:
+    import numpy as np
+
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_mlp_sigs(lib()).mlp_set_params(h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+           "mlp_set_params")
+
+
+def mlp_forward(h, x, n, y, stream=None) -> None:
+    _check(_mlp_sigs(lib()).mlp_forward(h, _dev_ptr(x, "float32", "x"), int(n), _dev_ptr(y, "float32", "y"),
+                                        _stream_handle(stream)), "mlp_forward")
+
+
+def mlp_train_step(h, x, t, idx, n, lr, loss=None, stream=None) -> None:
+    _check(_mlp_sigs(lib()).mlp_train_step(h, _dev_ptr(x, "float32", "x"), _dev_ptr(t, "float32", "t"),
+                                           _opt_ptr(idx, "int32", "idx"), int(n), float(lr),
+                                           _opt_ptr(loss, "float32", "loss"), _stream_handle(stream)),
+           "mlp_train_step")
+
+
+def mlp_backward(h, x, t, idx, n, grad, loss=None, stream=None) -> None:
+    _check(_mlp_sigs(lib()).mlp_backward(h, _dev_ptr(x, "float32", "x"), _dev_ptr(t, "float32", "t"),
+                                         _opt_ptr(idx, "int32", "idx"), int(n), _dev_ptr(grad, "float32", "grad"),
+                                         _opt_ptr(loss, "float32", "loss"), _stream_handle(stream)), "mlp_backward")
+
+
+def mlp_free(h) -> None:
+    _check(_mlp_sigs(lib()).mlp_free(h), "mlp_free")
+
+
+def me_features(momenta, n, npart, x, stream=None) -> None:
+    _check(_mlp_sigs(lib()).me_features(_dev_ptr(momenta, "float64", "momenta"), int(n), int(npart),
+                                        _dev_ptr(x, "float32", "x"), _stream_handle(stream)), "me_features")
+
+
+def unweight_two_stage(ctx, mlp, momenta, w_ps, n, uniforms, y_mu, y_sigma, s_max, r_max, out_idx, out_w,
+                       out_count, stream=None) -> None:
+    _check(_mlp_sigs(lib()).unweight_two_stage(
+        ctx, mlp, _dev_ptr(momenta, "float64", "momenta"), _dev_ptr(w_ps, "float64", "w_ps"), int(n),
+        _dev_ptr(uniforms, "float64", "uniforms"), float(y_mu), float(y_sigma), float(s_max), float(r_max),
+        _dev_ptr(out_idx, "int32", "out_idx"), _dev_ptr(out_w, "float64", "out_w"),
+        _dev_ptr(out_count, "int32", "out_count"), _stream_handle(stream)), "unweight_two_stage")
+
+
+class Surrogate:
+    """The network on the current GPU (wraps an mlp handle)."""
+
+    def __init__(self, n_in=24, width=256, depth=4, seed=1004):
+        self.n_in, self.width, self.depth = n_in, width, depth
+        self.h = mlp_create(n_in, width, depth, seed)
+
+    @property
+    def n_params(self):
+        return mlp_n_params(self.h)
+
+    def get_params(self):
+        return mlp_get_params(self.h)
+
+    def set_params(self, p):
+        mlp_set_params(self.h, p)
+
+    def forward(self, x, stream=None):
+        import torch
+
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        mlp_forward(self.h, x, x.shape[0], y, stream)
+        return y
+
+    def train_step(self, x, t, idx, lr, loss=None, stream=None):
+        n = idx.shape[0] if idx is not None else x.shape[0]
+        mlp_train_step(self.h, x, t, idx, n, lr, loss, stream)
+
+    def backward(self, x, t, idx=None, stream=None):
+        import torch
+
+        n = idx.shape[0] if idx is not None else x.shape[0]
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        mlp_backward(self.h, x, t, idx, n, g, loss, stream)
+        return g, loss
+
+    def close(self):
+        if self.h is not None:
+            mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def features(momenta, stream=None):
+    """Network inputs [n][4 npart] float32 from float64 momenta [n][npart][4]."""
+    import torch
+
+    n, npart = momenta.shape[0], momenta.shape[1]
+    x = torch.empty(n, 4 * npart, dtype=torch.float32, device=momenta.device)
+    me_features(momenta, n, npart, x, stream)
+    return x

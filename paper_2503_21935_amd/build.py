@@ -19,6 +19,11 @@ LIB = os.path.join(HERE, "libme.so")
 
 PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg"]
 
+# Calibration of the mixed form's amplitude error estimate (multiplies
+# u32 * 2 lambda_max(|N|) |S| |J| / Q); fixed by comparing float32 results
+# with the oracle (see the mixed-precision tests).
+MIXED_CEST = {"gg_tt": 8.0, "gg_ttg": 8.0, "gg_ttgg": 8.0, "gg_ttggg": 8.0}
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-variable",
@@ -29,22 +34,42 @@ HIPFLAGS = [
 ]
 
 _TU = """// Generated translation unit: kernels of {name}.
-#include "me_kernels.h"
+#include "me_mixed.h"
 {include}
 
 static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
                              const me_params& prm, double* qhel, hipStream_t s) {{
     const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
-    hipLaunchKernelGGL(({kernel}<{proc}, double>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
-                       qhel);
+    hipLaunchKernelGGL(({kernel}<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
+                       qhel, nullptr, nullptr);
     return hipGetLastError();
 }}
 
-#ifndef __HIP_DEVICE_COMPILE__  // the table entry holds a host function pointer
+static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                 const me_params& prm, const int* idx, const int* count, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL(({kernel}<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
+                       nullptr, idx, count);
+    return hipGetLastError();
+}}
+{mixed}
+#ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
 extern const me_process_desc me_desc_{name} = {{
     "{name}", {kind}, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
-    {proc}::flops_amp, {proc}::flops_colour, launch_f64}};
+    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, {mixed_ptr}, {cest}, {colerr}}};
 #endif
+"""
+
+_MIXED = """
+static hipError_t launch_mixed(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                               const me_params& prm, float tol, float cest, int* flag_count, int* flag_idx,
+                               float* err_out, unsigned char* flag_out, hipStream_t s) {{
+    if (flag_count) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, flag_count);
+    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL((k_me_gg_mixed<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm, tol,
+                       cest, flag_count, flag_idx, err_out, flag_out);
+    return hipGetLastError();
+}}
 """
 
 _REG = """// Generated process table.
@@ -77,16 +102,20 @@ def generate_sources(processes):
     for name in processes:
         if name == "ee_mumu":
             inc, kernel, proc, kind = "", "k_me_ee", "proc_ee_mumu", "ME_KIND_EE"
+            mixed, mixed_ptr, colerr = "", "nullptr", "0.0"
         else:
             inc, kernel, proc, kind = f'#include "gen/proc_{name}.h"', "k_me_gg", f"proc_{name}", "ME_KIND_GG"
+            mixed, mixed_ptr, colerr = _MIXED.format(proc=proc), "launch_mixed", f"{proc}::colour_err_f16"
         path = os.path.join(GEN, f"tu_{name}.hip")
-        _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind))
+        _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind, mixed=mixed,
+                                mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr))
         tus.append(path)
     decls = "\n".join(f"extern const me_process_desc me_desc_{n};" for n in processes)
     ptrs = ", ".join(f"&me_desc_{n}" for n in processes)
     reg = os.path.join(GEN, "registry.cpp")
     _write(reg, _REG.format(decls=decls, ptrs=ptrs))
-    return tus + [reg, os.path.join(CSRC, "me_api.cpp")], info
+    return tus + [reg, os.path.join(CSRC, "me_api.cpp"), os.path.join(CSRC, "mlp.hip"),
+                  os.path.join(CSRC, "me_unweight.hip")], info
 
 
 def _compile(src):

@@ -9,15 +9,16 @@
 #include <string>
 #include <vector>
 
-#include "../../include/me.h"
-#include "me_launch.h"
+#include "me_internal.h"
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const std::string& msg) {
+int me_fail(int code, const std::string& msg) {
     g_last_error = msg;
     return code;
 }
+
+static int fail(int code, const std::string& msg) { return me_fail(code, msg); }
 
 #define HIP_CHECK(expr)                                                                          \
     do {                                                                                         \
@@ -25,15 +26,21 @@ static int fail(int code, const std::string& msg) {
         if (_e != hipSuccess) return fail(ME_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
     } while (0)
 
-struct me_ctx {
-    const me_process_desc* proc;
-    me_params prm;
-    int device;
-    int nhel_good;
-    std::vector<int> good;  // host copy of the filtered helicities
-    int* d_good;            // device copy
-    int* d_all;             // device list 0..nhel-1
-};
+// Grow the flagged-event index list to hold nevt entries (synchronises the
+// device when it has to reallocate).
+static int ensure_scratch(me_ctx* c, int64_t nevt) {
+    if (!c->d_count) HIP_CHECK(hipMalloc(&c->d_count, sizeof(int)));
+    if (nevt > c->idx_cap) {
+        if (c->d_idx) {
+            HIP_CHECK(hipDeviceSynchronize());
+            HIP_CHECK(hipFree(c->d_idx));
+            c->d_idx = nullptr;
+        }
+        HIP_CHECK(hipMalloc(&c->d_idx, nevt * sizeof(int)));
+        c->idx_cap = nevt;
+    }
+    return ME_OK;
+}
 
 // ---------------------------------------------------------------------------
 // Probe points for the helicity filter: flat massless n-body momenta from a
@@ -168,6 +175,17 @@ int me_init(const char* process, const double* couplings, int n_couplings, const
     c->prm.wz = wz;
     c->d_good = nullptr;
     c->d_all = nullptr;
+    c->mode = ME_FP64;
+    c->tol = 1e-5;
+    c->d_count = nullptr;
+    c->d_idx = nullptr;
+    c->idx_cap = 0;
+    c->uw_x = nullptr;
+    c->uw_y = nullptr;
+    c->uw_s = nullptr;
+    c->uw_me2 = nullptr;
+    c->uw_idx1 = nullptr;
+    c->uw_cap = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) {
         delete c;
@@ -195,9 +213,51 @@ int me_eval(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, voi
     if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
     if (nevt == 0) return ME_OK;
     if (!momenta || !out_me2) return fail(ME_EINVAL, "null buffer");
-    if (nevt > (int64_t)ME_BLOCK * 0x7fffffffLL) return fail(ME_EINVAL, "nevt too large for one launch");
-    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr,
-                                  (hipStream_t)stream));
+    if (nevt > 0x7fffffffLL) return fail(ME_EINVAL, "nevt above 2^31 - 1");
+    hipStream_t s = (hipStream_t)stream;
+    if (c->mode == ME_MIXED && c->proc->launch_mixed) {
+        int rc = ensure_scratch(c, nevt);
+        if (rc != ME_OK) return rc;
+        HIP_CHECK(c->proc->launch_mixed(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, (float)c->tol,
+                                        (float)c->proc->mixed_cest, c->d_count, c->d_idx, nullptr, nullptr, s));
+        // float64 rerun of the flagged events, in place, on the same stream
+        HIP_CHECK(c->proc->launch_f64_idx(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, c->d_idx,
+                                          c->d_count, s));
+        return ME_OK;
+    }
+    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, s));
+    return ME_OK;
+}
+
+int me_set_precision(me_ctx* c, int mode, double rel_tol) {
+    if (!c) return fail(ME_EINVAL, "null context");
+    if (mode != ME_FP64 && mode != ME_MIXED) return fail(ME_EINVAL, "mode must be ME_FP64 or ME_MIXED");
+    if (mode == ME_MIXED && !(rel_tol > 0)) return fail(ME_EINVAL, "tolerance must be positive");
+    c->mode = mode;
+    if (mode == ME_MIXED) c->tol = rel_tol;
+    return ME_OK;
+}
+
+int me_eval_mixed_diag(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, float* out_err,
+                       uint8_t* out_flag, void* stream) {
+    if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
+    if (!c->proc->launch_mixed) return fail(ME_ESTATE, "the process has no mixed-precision form");
+    if (nevt == 0) return ME_OK;
+    if (!momenta || !out_me2 || !out_err || !out_flag) return fail(ME_EINVAL, "null buffer");
+    if (nevt > 0x7fffffffLL) return fail(ME_EINVAL, "nevt above 2^31 - 1");
+    HIP_CHECK(c->proc->launch_mixed(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, (float)c->tol,
+                                    (float)c->proc->mixed_cest, nullptr, nullptr, out_err, out_flag,
+                                    (hipStream_t)stream));
+    return ME_OK;
+}
+
+int me_fallback_count(me_ctx* c, int64_t* count) {
+    if (!c || !count) return fail(ME_EINVAL, "null argument");
+    *count = 0;
+    if (!c->d_count) return ME_OK;
+    int v = 0;
+    HIP_CHECK(hipMemcpy(&v, c->d_count, sizeof(int), hipMemcpyDeviceToHost));
+    *count = v;
     return ME_OK;
 }
 
@@ -233,11 +293,15 @@ int me_good_helicities(const me_ctx* c, int* out, int* count) {
 
 int me_free(me_ctx* c) {
     if (!c) return ME_OK;
-    hipError_t e1 = hipSuccess, e2 = hipSuccess;
-    if (c->d_good) e1 = hipFree(c->d_good);
-    if (c->d_all) e2 = hipFree(c->d_all);
+    hipError_t e = hipSuccess;
+    void* bufs[] = {c->d_good, c->d_all, c->d_count, c->d_idx, c->uw_x, c->uw_y, c->uw_s, c->uw_me2, c->uw_idx1};
+    for (void* b : bufs)
+        if (b) {
+            hipError_t r = hipFree(b);
+            if (r != hipSuccess) e = r;
+        }
     delete c;
-    if (e1 != hipSuccess || e2 != hipSuccess) return fail(ME_EDEVICE, "hipFree failed");
+    if (e != hipSuccess) return fail(ME_EDEVICE, std::string("hipFree: ") + hipGetErrorString(e));
     return ME_OK;
 }
 

@@ -37,44 +37,79 @@ MEV void load_event(const double* __restrict__ mom, int64_t ev, mom4<T>* p) {
 
 // qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
 // filter and for tests; entries of helicities not in the list are untouched.
+// Wavefunctions of one helicity in the amplitude type T (built in float64
+// from the momenta held in x: incoming gluons p = q, outgoing p = -q).
 template <class P, typename T>
-__global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ mom, int64_t nevt,
-                                                    double* __restrict__ out, const int* __restrict__ hels,
-                                                    int nh, me_params prm, double* __restrict__ qhel) {
-    const int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ev >= nevt) return;
+MEV void gg_externals(gg_ext<T, P::ngluon>& x, int h) {
     constexpr int NP = P::npart, NG = P::ngluon;
-    mom4<T> p[NP];
-    load_event<T, NP>(mom, ev, p);
-    gg_ext<T, NG> x;
-    x.m = T(prm.mt);
-    x.mw = T(prm.mt * prm.wt);
-    x.g = T(prm.gs);
+#pragma unroll
+    for (int a = 0; a < NG; ++a) {
+        const int ip = (a < 2) ? a : a + 2;
+        const vec4<double> e = gluon_eps((a < 2) ? x.q[a] : -x.q[a], helicity_of<NP>(h, ip), a >= 2);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x.eps[a].v[c] = to_t<T>(e.v[c]);
+    }
+    const spinor<double> u = bar(u_spinor(x.p3, x.m, helicity_of<NP>(h, 2)));
+    const spinor<double> v = v_spinor(x.p4, x.m, helicity_of<NP>(h, 3));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        x.ubar3.s[c] = to_t<T>(u.s[c]);
+        x.v4.s[c] = to_t<T>(v.s[c]);
+    }
+}
+
+template <class P, typename T>
+MEV void gg_opaque(gg_ext<T, P::ngluon>& x) {
+#pragma unroll
+    for (int a = 0; a < P::ngluon; ++a) opaque_mom(x.q[a]);
+    opaque_mom(x.p3);
+    opaque_mom(x.p4);
+}
+
+template <class P, typename T>
+MEV void gg_setup(gg_ext<T, P::ngluon>& x, const mom4<double>* p, const me_params& prm) {
+    x.m = prm.mt;
+    x.mw = prm.mt * prm.wt;
+    x.g = prm.gs;
+    x.mT = T(prm.mt);
+    x.gT = T(prm.gs);
     x.p3 = p[2];
     x.p4 = p[3];
 #pragma unroll
-    for (int a = 0; a < NG; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
+    for (int a = 0; a < P::ngluon; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
+}
+
+// qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
+// filter and for tests; entries of helicities not in the list are untouched.
+// idx (optional): evaluate only events idx[0..*count) (the float64 rerun of
+// events flagged by the mixed-precision kernel); out is indexed the same way.
+template <class P>
+__global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ mom, int64_t nevt,
+                                                    double* __restrict__ out, const int* __restrict__ hels,
+                                                    int nh, me_params prm, double* __restrict__ qhel,
+                                                    const int* __restrict__ idx, const int* __restrict__ count) {
+    int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count) {
+        if (ev >= *count) return;
+        ev = idx[ev];
+    } else if (ev >= nevt) {
+        return;
+    }
+    using T = double;
+    constexpr int NP = P::npart, NG = P::ngluon;
+    mom4<double> p[NP];
+    load_event<double, NP>(mom, ev, p);
+    gg_ext<T, NG> x;
+    gg_setup<P, T>(x, p, prm);
     T acc = T(0);
 #pragma unroll 1
     for (int ih = 0; ih < nh; ++ih) {
         const int h = hels[ih];
-        // Make the momenta opaque to the optimiser in every iteration: the
-        // helicity-independent subexpressions (subset momenta, propagator
-        // denominators) are then recomputed per helicity instead of being
-        // hoisted out of the loop, where they would occupy registers for the
-        // whole loop and force spills.
-        opaque(p, NP);
-        opaque_mom(x.p3);
-        opaque_mom(x.p4);
-#pragma unroll
-        for (int a = 0; a < NG; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
-#pragma unroll
-        for (int a = 0; a < NG; ++a) {
-            const int ip = (a < 2) ? a : a + 2;
-            x.eps[a] = gluon_eps(p[ip], helicity_of<NP>(h, ip), a >= 2);
-        }
-        x.ubar3 = bar(u_spinor(p[2], x.m, helicity_of<NP>(h, 2)));
-        x.v4 = v_spinor(p[3], x.m, helicity_of<NP>(h, 3));
+        // Opaque momenta in every iteration: the helicity-independent
+        // subexpressions are recomputed per helicity instead of being hoisted
+        // out of the loop, where they would occupy registers throughout.
+        gg_opaque<P, T>(x);
+        gg_externals<P, T>(x, h);
         cx<T> J[P::ncol];
 #pragma unroll
         for (int k = 0; k < P::ncol; ++k) J[k] = mk(T(0), T(0));
@@ -86,12 +121,19 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ m
     out[ev] = double(acc) * (1.0 / (256.0 * P::identical * P::lcd));
 }
 
-template <class P, typename T>
+template <class P>
 __global__ __launch_bounds__(ME_BLOCK) void k_me_ee(const double* __restrict__ mom, int64_t nevt,
                                                     double* __restrict__ out, const int* __restrict__ hels,
-                                                    int nh, me_params prm, double* __restrict__ qhel) {
-    const int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (ev >= nevt) return;
+                                                    int nh, me_params prm, double* __restrict__ qhel,
+                                                    const int* __restrict__ idx, const int* __restrict__ count) {
+    int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (count) {
+        if (ev >= *count) return;
+        ev = idx[ev];
+    } else if (ev >= nevt) {
+        return;
+    }
+    using T = double;
     mom4<T> p[P::npart];
     load_event<T, P::npart>(mom, ev, p);
     T acc = T(0);

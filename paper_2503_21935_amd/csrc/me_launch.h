@@ -11,6 +11,18 @@
 typedef hipError_t (*me_launch_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
                                    const me_params& prm, double* qhel, hipStream_t stream);
 
+// Indexed variant: evaluate events idx[0..*count) only (count on the device).
+typedef hipError_t (*me_launch_idx_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                       const me_params& prm, const int* idx, const int* count,
+                                       hipStream_t stream);
+
+// Mixed-precision form: float32 amplitudes, float16 hi/lo MFMA colour sum,
+// per-event error estimate; flagged events appended to flag_idx.
+typedef hipError_t (*me_launch_mixed_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                         const me_params& prm, float tol, float cest, int* flag_count,
+                                         int* flag_idx, float* err_out, unsigned char* flag_out,
+                                         hipStream_t stream);
+
 enum { ME_KIND_EE = 0, ME_KIND_GG = 1 };
 
 struct me_process_desc {
@@ -19,6 +31,10 @@ struct me_process_desc {
     int npart, ndiag, ncol, nhel;
     double flops_amp, flops_colour;  // per helicity
     me_launch_fn launch_f64;
+    me_launch_idx_fn launch_f64_idx;
+    me_launch_mixed_fn launch_mixed;  // nullptr: the process has no mixed form
+    double mixed_cest;                // calibration of the amplitude error estimate
+    double colour_err;                // a-priori error of the float16 hi/lo colour sum
 };
 
 const me_process_desc* me_find_process(const char* name);

@@ -11,16 +11,25 @@ struct me_params {
     double mz, wz;          // Z mass and width
 };
 
+// Device-side access to a process's colour-matrix numerators (specialised by
+// the generated process headers).
+template <class P>
+struct colour_table;
+
 // External wavefunctions and momenta of one event at one helicity for
 // g g -> t tbar + (NG-2) g.  Gluon momenta are counted as flowing into the
 // diagram (q = p for the two incoming gluons, q = -p for outgoing ones).
+// Momenta, propagator denominators and couplings stay in float64 for every
+// amplitude type T: the near-on-shell propagators cancel p^2 against m^2,
+// which float32 cannot resolve.
 template <typename T, int NG>
 struct gg_ext {
     vec4<T> eps[NG];
-    mom4<T> q[NG];
     spinor<T> ubar3, v4;
-    mom4<T> p3, p4;
-    T m, mw, g;  // top mass, mass * width, strong coupling
+    mom4<double> q[NG];
+    mom4<double> p3, p4;
+    double m, mw, g;  // top mass, mass * width, strong coupling
+    T mT, gT;         // the same in the amplitude type
 };
 
 // e+(p1) e-(p2) -> mu+(p3) mu-(p4) through an s-channel photon and Z:

@@ -84,6 +84,10 @@ MEV spinor<T> opq(spinor<T> a) {
     return a;
 }
 
+// Conversions from the float64 momentum algebra to the amplitude type.
+template <typename T> MEV mom4<T> to_t(const mom4<double>& p) { return {T(p.e), T(p.x), T(p.y), T(p.z)}; }
+template <typename T> MEV cx<T> to_t(const cx<double>& c) { return {T(c.r), T(c.i)}; }
+
 template <typename T> MEV T msq(mom4<T> p) { return p.e * p.e - p.x * p.x - p.y * p.y - p.z * p.z; }
 
 // Minkowski product of complex 4-vectors

@@ -1,0 +1,602 @@
+// mlp.hip -- surrogate network kernels: BF16 matrix-core GEMMs with FP32
+// accumulation and fused epilogues, loss, reductions, Adam; the C ABI of
+// include/mlp.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlp.h"
+#include "me_internal.h"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define MLP_KPAD 32  // first-layer inputs padded to one MFMA K step
+
+// ---------------------------------------------------------------------------
+// GEMM: C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m * a_sm + k * a_sk],
+// B(k, n) = B[k * b_sk + n * b_sn], BF16 operands, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  A 256-thread block computes a 64 x 64 tile, each
+// wave 32 x 32 (2 x 2 MFMA tiles).  Fragment layouts (16x16x32): lane l holds
+// A[l%16][8(l/16) .. +7], B[8(l/16) .. +7][l%16] and D[4(l/16) + v][l%16].
+// Requirements: K % 32 == 0; rows/columns beyond M/N are computed on clamped
+// operands and not stored.
+// ---------------------------------------------------------------------------
+enum { EPI_FWD_TRAIN = 0, EPI_FWD_INFER = 1, EPI_BWD_DH = 2, EPI_DW = 3 };
+
+struct epi_args {
+    const float* bias;  // FWD: [N]
+    float* z;           // FWD_TRAIN: pre-activations [M][N]
+    bf16* h;            // FWD: activations [M][ldh]
+    int ldh;
+    const float* zprev; // BWD_DH: pre-activations of the previous layer [M][N]
+    bf16* dz;           // BWD_DH: output gradient w.r.t. those pre-activations [M][N]
+    float* g;           // DW: gradient [M][N] row-major with leading dimension ldg
+    int ldg;
+    int ncols_store;    // DW: columns actually stored (n_in for the first layer)
+};
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
+
+template <bool AK1, bool BK1>
+__device__ __forceinline__ void load_frags(const bf16* __restrict__ A, int64_t a_sm, int64_t a_sk,
+                                           const bf16* __restrict__ B, int64_t b_sk, int64_t b_sn, int row0,
+                                           int col0, int k0, int M, int N, int lane, bf16x8 (&a)[2],
+                                           bf16x8 (&b)[2]) {
+    const int kk = k0 + 8 * (lane >> 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        int r = row0 + 16 * i + (lane & 15);
+        r = r < M ? r : M - 1;
+        const bf16* p = A + (int64_t)r * a_sm + (int64_t)kk * a_sk;
+        if constexpr (AK1) {
+            a[i] = *reinterpret_cast<const bf16x8*>(p);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) a[i][v] = p[(int64_t)v * a_sk];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        int c = col0 + 16 * j + (lane & 15);
+        c = c < N ? c : N - 1;
+        const bf16* p = B + (int64_t)kk * b_sk + (int64_t)c * b_sn;
+        if constexpr (BK1) {
+            b[j] = *reinterpret_cast<const bf16x8*>(p);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) b[j][v] = p[(int64_t)v * b_sk];
+        }
+    }
+}
+
+template <int EPI, bool AK1, bool BK1>
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, int64_t a_sm,
+                                              int64_t a_sk, const bf16* __restrict__ B, int64_t b_sk,
+                                              int64_t b_sn, epi_args e) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
+    const int col0 = blockIdx.x * 64 + (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[2], b[2];
+        load_frags<AK1, BK1>(A, a_sm, a_sk, B, b_sk, b_sn, row0, col0, k0, M, N, lane, a, b);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = col0 + 16 * j + (lane & 15);
+            if (c >= N) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = row0 + 16 * i + 4 * (lane >> 4) + v;
+                if (r >= M) continue;
+                const float x = acc[i][j][v];
+                if constexpr (EPI == EPI_FWD_TRAIN || EPI == EPI_FWD_INFER) {
+                    const float z = x + e.bias[c];
+                    if constexpr (EPI == EPI_FWD_TRAIN) e.z[(int64_t)r * N + c] = z;
+                    e.h[(int64_t)r * e.ldh + c] = (bf16)(z * sigmoidf_(z));
+                } else if constexpr (EPI == EPI_BWD_DH) {
+                    const float z = e.zprev[(int64_t)r * N + c];
+                    const float s = sigmoidf_(z);
+                    e.dz[(int64_t)r * N + c] = (bf16)(x * s * (1.f + z * (1.f - s)));
+                } else {
+                    if (c < e.ncols_store) e.g[(int64_t)r * e.ldg + c] = x;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise and reduction kernels
+// ---------------------------------------------------------------------------
+
+// X[j][k] = bf16(x[src(j)][k]) for k < n_in, zero for n_in <= k < 32.
+__global__ void k_prep_input(const float* __restrict__ x, const int32_t* __restrict__ idx, int64_t n, int n_in,
+                             bf16* __restrict__ X) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int64_t src = idx ? idx[j] : j;
+    for (int k = 0; k < MLP_KPAD; ++k) X[j * MLP_KPAD + k] = (bf16)(k < n_in ? x[src * n_in + k] : 0.f);
+}
+
+// y[m] = sum_k H[m][k] w[k] + b (FP32 accumulation)
+__global__ void k_last_fwd(const bf16* __restrict__ H, int64_t M, int width, const float* __restrict__ w,
+                           const float* __restrict__ b, float* __restrict__ y) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const bf16x8* h = reinterpret_cast<const bf16x8*>(H + m * width);
+    float s = 0.f;
+    for (int k8 = 0; k8 < width / 8; ++k8) {
+        const bf16x8 v = h[k8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s = fmaf((float)v[q], w[8 * k8 + q], s);
+    }
+    y[m] = s + b[0];
+}
+
+// dy[m] = 2 (y[m] - t[src(m)]) / M; per-block partial sums of the squared residual.
+__global__ void k_loss(const float* __restrict__ y, const float* __restrict__ t, const int32_t* __restrict__ idx,
+                       int64_t M, float* __restrict__ dy, float* __restrict__ partial) {
+    __shared__ float red[256];
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float r2 = 0.f;
+    if (m < M) {
+        const float r = y[m] - t[idx ? idx[m] : m];
+        dy[m] = 2.f * r / (float)M;
+        r2 = r * r;
+    }
+    red[threadIdx.x] = r2;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(const float* __restrict__ partial, int nblocks, int64_t M, float* __restrict__ loss) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < nblocks; i += 256) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (float)M;
+}
+
+// dZ[m][n] = bf16(dy[m] w[n] silu'(Z[m][n]))
+__global__ void k_last_bwd(const float* __restrict__ dy, const float* __restrict__ w, const float* __restrict__ Z,
+                           int64_t M, int width, bf16* __restrict__ dZ) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * width) return;
+    const int64_t m = i / width;
+    const int n = (int)(i % width);
+    const float z = Z[i];
+    const float s = sigmoidf_(z);
+    dZ[i] = (bf16)(dy[m] * w[n] * s * (1.f + z * (1.f - s)));
+}
+
+// out[n] = sum_m coef(m) A[m][n], coef = dy[m] or 1; one block per 64 columns.
+template <typename TA>
+__global__ void k_colsum(const TA* __restrict__ A, const float* __restrict__ coef, int64_t M, int N,
+                         float* __restrict__ out) {
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int rg = threadIdx.x >> 6;
+    float s = 0.f;
+    if (c < N)
+        for (int64_t m = rg; m < M; m += 4) s = fmaf(coef ? coef[m] : 1.f, (float)A[m * N + c], s);
+    red[rg][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rg == 0 && c < N) out[c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// out[0] = sum_m dy[m]
+__global__ void k_sum(const float* __restrict__ v, int64_t M, float* __restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t m = threadIdx.x; m < M; m += 256) s += v[m];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+struct layer_map {
+    int64_t w_off[16], b_off[16];
+    int fan_in[16];
+};
+
+// Adam with bias correction on the flat FP32 parameters, then the BF16 copies
+// of the weight matrices (first layer padded to 32 inputs).
+__global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int64_t np, float lr, float c1, float c2, layer_map L,
+                       int depth, int width, bf16* const* __restrict__ wbf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const float gi = g[i];
+    const float mi = 0.9f * m[i] + 0.1f * gi;
+    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float th = theta[i] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    theta[i] = th;
+    for (int l = 0; l < depth; ++l) {
+        const int64_t o = L.w_off[l];
+        const int fi = L.fan_in[l];
+        if (i >= o && i < o + (int64_t)width * fi) {
+            const int64_t r = (i - o) / fi, k = (i - o) % fi;
+            const int ld = (l == 0) ? MLP_KPAD : fi;
+            wbf[l][r * ld + k] = (bf16)th;
+        }
+    }
+}
+
+// BF16 copies from the master parameters (after set_params / init)
+__global__ void k_to_bf16(const float* __restrict__ theta, int64_t o, int rows, int fi, int ld, bf16* __restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * ld) return;
+    const int64_t r = i / ld, k = i % ld;
+    w[i] = (bf16)(k < fi ? theta[o + r * fi + k] : 0.f);
+}
+
+__global__ void k_features(const double* __restrict__ mom, int64_t n, int npart, float* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* p = mom + i * npart * 4;
+    const double E = p[0] + p[4], px = p[1] + p[5], py = p[2] + p[6], pz = p[3] + p[7];
+    const double inv = 1.0 / sqrt(E * E - px * px - py * py - pz * pz);
+    for (int c = 0; c < 4 * npart; ++c) x[i * 4 * npart + c] = (float)(p[c] * inv);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct me_mlp {
+    int n_in, width, depth;
+    int64_t np;
+    layer_map L;
+    int64_t wout_off, bout_off;
+    float *theta, *grad, *m, *v;
+    std::vector<bf16*> wbf;  // per hidden layer, [width][ld]
+    bf16** d_wbf;            // device array of those pointers
+    int64_t cap;             // activation capacity (rows)
+    bf16* X;
+    std::vector<bf16*> H;
+    std::vector<float*> Z;
+    bf16 *dZa, *dZb;
+    float *y, *dy, *partial, *loss_tmp;
+    int64_t step;
+};
+
+#define HCHK(expr)                                                                                   \
+    do {                                                                                             \
+        hipError_t _e = (expr);                                                                      \
+        if (_e != hipSuccess) return me_fail(ME_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+static uint64_t splitmix(uint64_t& s) {
+    s += 0x9E3779B97F4A7C15ull;
+    uint64_t z = s;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static void free_acts(me_mlp* p) {
+    auto f = [](void* q) {
+        if (q) (void)hipFree(q);
+    };
+    f(p->X);
+    for (auto q : p->H) f(q);
+    for (auto q : p->Z) f(q);
+    f(p->dZa);
+    f(p->dZb);
+    f(p->y);
+    f(p->dy);
+    f(p->partial);
+    p->X = nullptr;
+    p->H.assign(p->depth, nullptr);
+    p->Z.assign(p->depth, nullptr);
+    p->dZa = p->dZb = nullptr;
+    p->y = p->dy = p->partial = nullptr;
+    p->cap = 0;
+}
+
+static int ensure_acts(me_mlp* p, int64_t rows) {
+    if (rows <= p->cap) return ME_OK;
+    HCHK(hipDeviceSynchronize());
+    free_acts(p);
+    const int64_t W = p->width;
+    HCHK(hipMalloc(&p->X, rows * MLP_KPAD * sizeof(bf16)));
+    for (int l = 0; l < p->depth; ++l) {
+        HCHK(hipMalloc(&p->H[l], rows * W * sizeof(bf16)));
+        HCHK(hipMalloc(&p->Z[l], rows * W * sizeof(float)));
+    }
+    HCHK(hipMalloc(&p->dZa, rows * W * sizeof(bf16)));
+    HCHK(hipMalloc(&p->dZb, rows * W * sizeof(bf16)));
+    HCHK(hipMalloc(&p->y, rows * sizeof(float)));
+    HCHK(hipMalloc(&p->dy, rows * sizeof(float)));
+    HCHK(hipMalloc(&p->partial, ((rows + 255) / 256 + 1) * sizeof(float)));
+    p->cap = rows;
+    return ME_OK;
+}
+
+static hipError_t refresh_bf16(me_mlp* p, hipStream_t s) {
+    for (int l = 0; l < p->depth; ++l) {
+        const int fi = p->L.fan_in[l], ld = (l == 0) ? MLP_KPAD : fi;
+        const int64_t tot = (int64_t)p->width * ld;
+        hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p->theta, p->L.w_off[l],
+                           p->width, fi, ld, p->wbf[l]);
+    }
+    return hipGetLastError();
+}
+
+template <int EPI, bool AK1, bool BK1>
+static void gemm(hipStream_t s, int M, int N, int K, const bf16* A, int64_t a_sm, int64_t a_sk, const bf16* B,
+                 int64_t b_sk, int64_t b_sn, const epi_args& e) {
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
+    hipLaunchKernelGGL((k_gemm<EPI, AK1, BK1>), grid, dim3(256), 0, s, M, N, K, A, a_sm, a_sk, B, b_sk, b_sn, e);
+}
+
+// Forward over rows [0, M) of p->X; training keeps Z and every H.
+static void forward(me_mlp* p, int64_t M, bool train, hipStream_t s) {
+    const int W = p->width;
+    const bf16* in = p->X;
+    int ld_in = MLP_KPAD, K = MLP_KPAD;
+    for (int l = 0; l < p->depth; ++l) {
+        epi_args e{};
+        e.bias = p->theta + p->L.b_off[l];
+        e.z = train ? p->Z[l] : nullptr;
+        bf16* out = train ? p->H[l] : ((l & 1) ? p->dZb : p->dZa);  // inference ping-pongs
+        e.h = out;
+        e.ldh = W;
+        // Z = in . W_l^T: A = in [M][K] (k contiguous), B(k, n) = W_l[n][k] (k contiguous)
+        if (train)
+            gemm<EPI_FWD_TRAIN, true, true>(s, (int)M, W, K, in, ld_in, 1, p->wbf[l], 1, K, e);
+        else
+            gemm<EPI_FWD_INFER, true, true>(s, (int)M, W, K, in, ld_in, 1, p->wbf[l], 1, K, e);
+        in = out;
+        ld_in = W;
+        K = W;
+    }
+    hipLaunchKernelGGL(k_last_fwd, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, in, M, W,
+                       p->theta + p->wout_off, p->theta + p->bout_off, p->y);
+}
+
+// Loss and gradients (into p->grad) for rows [0, M) with targets t[idx].
+static void backward(me_mlp* p, const float* t, const int32_t* idx, int64_t M, float* loss, hipStream_t s) {
+    const int W = p->width;
+    const unsigned nb = (unsigned)((M + 255) / 256);
+    hipLaunchKernelGGL(k_loss, dim3(nb), dim3(256), 0, s, p->y, t, idx, M, p->dy, p->partial);
+    if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, p->partial, (int)nb, M, loss);
+    bf16* Hl = p->H[p->depth - 1];
+    // output layer: dw_out = sum_m dy[m] H[m][:], db_out = sum dy
+    hipLaunchKernelGGL((k_colsum<bf16>), dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, Hl, p->dy, M, W,
+                       p->grad + p->wout_off);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, p->dy, M, p->grad + p->bout_off);
+    hipLaunchKernelGGL(k_last_bwd, dim3((unsigned)((M * W + 255) / 256)), dim3(256), 0, s, p->dy,
+                       p->theta + p->wout_off, p->Z[p->depth - 1], M, W, p->dZa);
+    bf16* dz = p->dZa;
+    bf16* dz_next = p->dZb;
+    for (int l = p->depth - 1; l >= 0; --l) {
+        const bf16* hin = (l == 0) ? p->X : p->H[l - 1];
+        const int fi = p->L.fan_in[l], ldin = (l == 0) ? MLP_KPAD : W;
+        // dW_l[n][k] = sum_m dZ[m][n] hin[m][k]: A(n, m) = dZ[m][n], B(m, k) = hin[m][k]
+        epi_args e{};
+        e.g = p->grad + p->L.w_off[l];
+        e.ldg = fi;
+        e.ncols_store = fi;
+        gemm<EPI_DW, false, false>(s, W, ldin, (int)M, dz, 1, W, hin, ldin, 1, e);
+        hipLaunchKernelGGL((k_colsum<bf16>), dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, dz, nullptr, M, W,
+                           p->grad + p->L.b_off[l]);
+        if (l > 0) {
+            // dH_{l-1}[m][k] = sum_n dZ[m][n] W_l[n][k]; fused silu'(Z_{l-1})
+            epi_args e2{};
+            e2.zprev = p->Z[l - 1];
+            e2.dz = dz_next;
+            gemm<EPI_BWD_DH, true, false>(s, (int)M, W, W, dz, W, 1, p->wbf[l], W, 1, e2);
+            bf16* tmp = dz;
+            dz = dz_next;
+            dz_next = tmp;
+        }
+    }
+}
+
+extern "C" {
+
+int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
+    if (!out || n_in < 1 || n_in > MLP_KPAD || width < 64 || width % 64 || width > 1024 || depth < 1 || depth > 16)
+        return me_fail(ME_EINVAL, "mlp_create: need 1 <= n_in <= 32, width a multiple of 64 up to 1024, depth 1..16");
+    me_mlp* p = new (std::nothrow) me_mlp();
+    if (!p) return me_fail(ME_ENOMEM, "host allocation");
+    p->n_in = n_in;
+    p->width = width;
+    p->depth = depth;
+    int64_t o = 0;
+    int fi = n_in;
+    for (int l = 0; l < depth; ++l) {
+        p->L.w_off[l] = o;
+        p->L.fan_in[l] = fi;
+        o += (int64_t)width * fi;
+        p->L.b_off[l] = o;
+        o += width;
+        fi = width;
+    }
+    p->wout_off = o;
+    o += width;
+    p->bout_off = o;
+    o += 1;
+    p->np = o;
+    p->H.assign(depth, nullptr);
+    p->Z.assign(depth, nullptr);
+    p->wbf.assign(depth, nullptr);
+    std::vector<float> h(o, 0.f);
+    uint64_t st = seed;
+    for (int l = 0; l < depth; ++l) {
+        const double a = std::sqrt(6.0 / p->L.fan_in[l]);
+        for (int64_t i = 0; i < (int64_t)width * p->L.fan_in[l]; ++i)
+            h[p->L.w_off[l] + i] = (float)(a * (2.0 * ((splitmix(st) >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+    }
+    {
+        const double a = std::sqrt(6.0 / width);
+        for (int64_t i = 0; i < width; ++i)
+            h[p->wout_off + i] = (float)(a * (2.0 * ((splitmix(st) >> 11) * (1.0 / 9007199254740992.0)) - 1.0));
+    }
+    auto bad = [&](hipError_t e) {
+        if (e != hipSuccess) {
+            mlp_free(p);
+            return true;
+        }
+        return false;
+    };
+    if (bad(hipMalloc(&p->theta, o * sizeof(float))) || bad(hipMalloc(&p->grad, o * sizeof(float))) ||
+        bad(hipMalloc(&p->m, o * sizeof(float))) || bad(hipMalloc(&p->v, o * sizeof(float))))
+        return me_fail(ME_ENOMEM, "mlp_create: device allocation");
+    for (int l = 0; l < depth; ++l) {
+        const int ld = (l == 0) ? MLP_KPAD : p->L.fan_in[l];
+        if (bad(hipMalloc(&p->wbf[l], (size_t)width * ld * sizeof(bf16))))
+            return me_fail(ME_ENOMEM, "mlp_create: device allocation");
+    }
+    if (bad(hipMalloc(&p->d_wbf, depth * sizeof(bf16*))) ||
+        bad(hipMemcpy(p->d_wbf, p->wbf.data(), depth * sizeof(bf16*), hipMemcpyHostToDevice)) ||
+        bad(hipMemcpy(p->theta, h.data(), o * sizeof(float), hipMemcpyHostToDevice)) ||
+        bad(hipMemset(p->m, 0, o * sizeof(float))) || bad(hipMemset(p->v, 0, o * sizeof(float))) ||
+        bad(hipMemset(p->grad, 0, o * sizeof(float))) || bad(refresh_bf16(p, nullptr)) ||
+        bad(hipDeviceSynchronize()))
+        return me_fail(ME_EDEVICE, "mlp_create: initialisation");
+    p->step = 0;
+    *out = p;
+    return ME_OK;
+}
+
+int mlp_n_params(const me_mlp* p, int64_t* n) {
+    if (!p || !n) return me_fail(ME_EINVAL, "null argument");
+    *n = p->np;
+    return ME_OK;
+}
+
+int mlp_get_params(me_mlp* p, float* host, int64_t n) {
+    if (!p || !host || n != p->np) return me_fail(ME_EINVAL, "mlp_get_params: null or wrong size");
+    HCHK(hipDeviceSynchronize());
+    HCHK(hipMemcpy(host, p->theta, n * sizeof(float), hipMemcpyDeviceToHost));
+    return ME_OK;
+}
+
+int mlp_set_params(me_mlp* p, const float* host, int64_t n) {
+    if (!p || !host || n != p->np) return me_fail(ME_EINVAL, "mlp_set_params: null or wrong size");
+    HCHK(hipDeviceSynchronize());
+    HCHK(hipMemcpy(p->theta, host, n * sizeof(float), hipMemcpyHostToDevice));
+    HCHK(refresh_bf16(p, nullptr));
+    HCHK(hipDeviceSynchronize());
+    return ME_OK;
+}
+
+int mlp_forward(me_mlp* p, const float* x, int64_t n, float* y, void* stream) {
+    if (!p || n < 0) return me_fail(ME_EINVAL, "mlp_forward: null or negative n");
+    if (n == 0) return ME_OK;
+    if (!x || !y) return me_fail(ME_EINVAL, "mlp_forward: null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t chunk = 1 << 16;
+    int rc = ensure_acts(p, std::min<int64_t>(n, chunk));
+    if (rc != ME_OK) return rc;
+    for (int64_t o = 0; o < n; o += chunk) {
+        const int64_t m = std::min<int64_t>(chunk, n - o);
+        hipLaunchKernelGGL(k_prep_input, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, x + o * p->n_in,
+                           nullptr, m, p->n_in, p->X);
+        forward(p, m, false, s);
+        HCHK(hipMemcpyAsync(y + o, p->y, m * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    HCHK(hipGetLastError());
+    return ME_OK;
+}
+
+static int grad_common(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float* loss,
+                       hipStream_t s) {
+    if (!p || !x || !t || n <= 0 || n % 64) return me_fail(ME_EINVAL, "batch must be a positive multiple of 64");
+    int rc = ensure_acts(p, n);
+    if (rc != ME_OK) return rc;
+    hipLaunchKernelGGL(k_prep_input, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, idx, n, p->n_in, p->X);
+    forward(p, n, true, s);
+    backward(p, t, idx, n, loss, s);
+    HCHK(hipGetLastError());
+    return ME_OK;
+}
+
+int mlp_backward(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float* grad_dev,
+                 float* loss_dev, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = grad_common(p, x, t, idx, n, loss_dev, s);
+    if (rc != ME_OK) return rc;
+    if (grad_dev) HCHK(hipMemcpyAsync(grad_dev, p->grad, p->np * sizeof(float), hipMemcpyDeviceToDevice, s));
+    return ME_OK;
+}
+
+int mlp_train_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float lr,
+                   float* loss_dev, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = grad_common(p, x, t, idx, n, loss_dev, s);
+    if (rc != ME_OK) return rc;
+    p->step += 1;
+    const float c1 = 1.f - std::pow(0.9f, (float)p->step), c2 = 1.f - std::pow(0.999f, (float)p->step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, s, p->theta, p->m, p->v, p->grad,
+                       p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf);
+    HCHK(hipGetLastError());
+    return ME_OK;
+}
+
+int mlp_free(me_mlp* p) {
+    if (!p) return ME_OK;
+    (void)hipDeviceSynchronize();
+    free_acts(p);
+    auto f = [](void* q) {
+        if (q) (void)hipFree(q);
+    };
+    f(p->theta);
+    f(p->grad);
+    f(p->m);
+    f(p->v);
+    for (auto q : p->wbf) f(q);
+    f(p->d_wbf);
+    delete p;
+    return ME_OK;
+}
+
+int me_features(const double* momenta, int64_t n, int npart, float* x, void* stream) {
+    if (n < 0 || npart < 2 || npart > 8) return me_fail(ME_EINVAL, "me_features: bad size");
+    if (n == 0) return ME_OK;
+    if (!momenta || !x) return me_fail(ME_EINVAL, "me_features: null buffer");
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, momenta, n,
+                       npart, x);
+    HCHK(hipGetLastError());
+    return ME_OK;
+}
+
+}  // extern "C"
+
+// helper for the unweighting driver in me_unweight.hip
+int mlp_forward_internal(me_mlp* p, const float* x, int64_t n, float* y, hipStream_t s) {
+    return mlp_forward(p, x, n, y, s);
+}
+int mlp_n_in(const me_mlp* p) { return p->n_in; }

@@ -12,9 +12,12 @@ from .emit import GGEmitter
 
 GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # Maximum number of wavefunctions kept alive at once by the emitted program
-# (more are recomputed): chosen so that the float64 kernels keep their working
-# set in registers without scratch spills.
-LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 6, "gg_ttggg": 6}
+# (more are recomputed).  Chosen per process by compiling and counting
+# float64 operations plus VGPR<->AGPR moves (both take a VALU issue slot):
+# g g -> t tbar g g is cheapest at 10 without scratch spills (12 and above
+# spill); the float32 program fits without any recomputation.
+LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 10, "gg_ttggg": 6}
+LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 
 
 def generate(outdir: str, processes=None, merge: bool = True) -> dict:
@@ -23,7 +26,7 @@ def generate(outdir: str, processes=None, merge: bool = True) -> dict:
     for name, n in GG_PROCESSES.items():
         if processes and name not in processes:
             continue
-        em = GGEmitter(name, n, merge=merge, cap=LIVE_CAP[name])
+        em = GGEmitter(name, n, merge=merge, cap=LIVE_CAP[name], cap_f32=LIVE_CAP_F32[name])
         src = em.render()
         path = os.path.join(outdir, f"proc_{name}.h")
         old = open(path).read() if os.path.exists(path) else None

@@ -41,9 +41,10 @@ def _coef_ops(c):
 class GGEmitter:
     """g g -> t tbar + (n-2) gluons."""
 
-    def __init__(self, name: str, n: int, merge: bool = True, cap: int = 8):
+    def __init__(self, name: str, n: int, merge: bool = True, cap: int = 8, cap_f32: int = None):
         self.name = name
         self.cap = cap
+        self.cap_f32 = cap_f32 if cap_f32 is not None else cap
         self.n = n
         self.plan = Plan(n, merge)
         self.perms = orderings(n)
@@ -220,6 +221,50 @@ class GGEmitter:
     # ------------------------------------------------------------------
     # emission of one node
     # ------------------------------------------------------------------
+    def node_momenta(self, node):
+        """Names of the momenta a node's code reads."""
+        kind = node[0]
+        names = set()
+
+        def add(S):
+            names.update(f"q{a}" for a in S)
+
+        def add_terms(terms):
+            for coef, k, kids, ch in terms:
+                if k == "v3":
+                    for c in kids:
+                        add(self.leaves_of(c))
+
+        if kind == "c":
+            c = self.plan.currents[node[1]]
+            add(c.leaves)
+            add_terms(c.terms)
+        elif kind in ("L", "R"):
+            key = node[1]
+            S = set()
+            for b in key:
+                S |= set(self.leaves_of(b))
+            if kind == "R":
+                S = set(range(self.n)) - S
+            rest = set(range(self.n)) - S
+            nin = lambda X: sum(1 for a in X if a < 2)
+            if S and (not rest or nin(S) <= nin(rest)):
+                add(S)
+                names.add("p3")
+            elif not S:
+                names.add("p3")
+            else:
+                add(rest)
+                names.add("p4")
+        elif kind == "vt":
+            names.update(("p3", "p4"))
+        else:
+            amp = self.plan.amps[node[1]]
+            if amp["kind"] == "root":
+                add_terms(amp["terms"])
+        order = [f"q{a}" for a in range(self.n)] + ["p3", "p4"]
+        return [x for x in order if x in names]
+
     def new_name(self, node):
         self.counter += 1
         kind = node[0]
@@ -241,8 +286,8 @@ class GGEmitter:
             for coef, kind, kids, ch in group:
                 if kind == "v3":
                     a, b = kids
-                    expr = (f"vvv({self.cur(a)}, {self.qexpr(self.leaves_of(a))}, "
-                            f"{self.cur(b)}, {self.qexpr(self.leaves_of(b))})")
+                    expr = (f"vvv({self.cur(a)}, to_t<T>({self.qexpr(self.leaves_of(a))}), "
+                            f"{self.cur(b)}, to_t<T>({self.qexpr(self.leaves_of(b))}))")
                     self.flops += FLOPS["vvv"]
                 else:
                     a, b, cc = kids
@@ -263,29 +308,31 @@ class GGEmitter:
 
     def emit_node(self, node):
         kind = node[0]
-        # New SSA names for the momenta before every node: helicity-independent
+        # New SSA names for the momenta this node reads: helicity-independent
         # subexpressions (subset sums, propagator denominators) are recomputed
         # where needed instead of being merged into long-lived registers.
-        self.w("fence(" + ", ".join(self.mom_names) + ");")
+        used = self.node_momenta(node)
+        if used:
+            self.w("fence(" + ", ".join(used) + ");")
         if kind == "c":
             c = self.plan.currents[node[1]]
             self.w(f"// gluon current over {sorted(c.leaves)} ({len(c.terms)} vertex terms)")
             self.w("vec4<T> " + self.new_name(node) + ";")
             nm = self.names[node]
             self.w("{")
-            self.w(f"    const T iq2 = T(1) / msq({self.qexpr(c.leaves)});")
+            self.w(f"    const T iq2 = T(1.0 / msq({self.qexpr(c.leaves)}));")
             self.flops += FLOPS["msq"] + FLOPS["recip"]
             parts = self.vertex_sum(c.terms)
             # W = (-i g / Q^2) s3 + (-g^2 / Q^2) s4
             if "s3" in parts and "s4" in parts:
-                self.w(f"    {nm} = vscale(mk(T(0), -x.g * iq2), s3);")
-                self.w(f"    vacc({nm}, mk(-x.g * x.g * iq2, T(0)), s4);")
+                self.w(f"    {nm} = vscale(mk(T(0), -x.gT * iq2), s3);")
+                self.w(f"    vacc({nm}, mk(-x.gT * x.gT * iq2, T(0)), s4);")
                 self.flops += FLOPS["vscale_c"] + 32
             elif "s3" in parts:
-                self.w(f"    {nm} = vscale(mk(T(0), -x.g * iq2), s3);")
+                self.w(f"    {nm} = vscale(mk(T(0), -x.gT * iq2), s3);")
                 self.flops += FLOPS["vscale_c"]
             else:
-                self.w(f"    {nm} = vscale(-x.g * x.g * iq2, s4);")
+                self.w(f"    {nm} = vscale(-x.gT * x.gT * iq2, s4);")
                 self.flops += FLOPS["vscale_r"]
             self.w("}")
         elif kind == "L":
@@ -299,9 +346,9 @@ class GGEmitter:
             # L' = L (i g gamma.W) i (P + m)/D  with P = p3 - Q_union
             self.w(f"spinor<T> {nm};")
             self.w("{")
-            self.w(f"    const mom4<T> P = {self.prop_momentum(S)};")
-            self.w("    const cx<T> f = x.g * crecip(msq(P) - x.m * x.m, x.mw);  // g/D")
-            self.w(f"    {nm} = scale(-f, row_prop(row_slash({src}, {self.cur(last)}), P, x.m));")
+            self.w(f"    const mom4<double> P = {self.prop_momentum(S)};")
+            self.w("    const cx<T> f = to_t<T>(x.g * crecip(msq(P) - x.m * x.m, x.mw));  // g/D")
+            self.w(f"    {nm} = scale(-f, row_prop(row_slash({src}, {self.cur(last)}), to_t<T>(P), x.mT));")
             self.w("}")
             self.flops += FLOPS["mom_add"] + FLOPS["msq"] + 2 + FLOPS["crecip"] + 2 + FLOPS["row_slash"] + \
                 FLOPS["row_prop"] + FLOPS["scale_sp"]
@@ -316,23 +363,27 @@ class GGEmitter:
             # R' = i (P + m)/D (i g gamma.W) R  with P = Q_union - p4
             self.w(f"spinor<T> {nm};")
             self.w("{")
-            self.w(f"    const mom4<T> P = {self.prop_momentum(set(range(self.n)) - S)};")
-            self.w("    const cx<T> f = x.g * crecip(msq(P) - x.m * x.m, x.mw);  // g/D")
-            self.w(f"    {nm} = scale(-f, prop_col(P, x.m, slash_col({self.cur(first)}, {src})));")
+            self.w(f"    const mom4<double> P = {self.prop_momentum(set(range(self.n)) - S)};")
+            self.w("    const cx<T> f = to_t<T>(x.g * crecip(msq(P) - x.m * x.m, x.mw));  // g/D")
+            self.w(f"    {nm} = scale(-f, prop_col(to_t<T>(P), x.mT, slash_col({self.cur(first)}, {src})));")
             self.w("}")
             self.flops += FLOPS["mom_add"] + FLOPS["msq"] + 2 + FLOPS["crecip"] + 2 + FLOPS["slash_col"] + \
                 FLOPS["prop_col"] + FLOPS["scale_sp"]
         elif kind == "vt":
             nm = self.new_name(node)
             self.w("// t tbar current (g/Q_T^2) ubar gamma v, Q_T = p3 + p4")
-            self.w(f"const vec4<T> {nm} = vscale(x.g / msq(p3 + p4), fbar_gamma_f(opq(x.ubar3), opq(x.v4)));")
+            self.w(f"const vec4<T> {nm} = vscale(T(x.g / msq(p3 + p4)), fbar_gamma_f(opq(x.ubar3), opq(x.v4)));")
             self.flops += FLOPS["mom_add"] + FLOPS["msq"] + FLOPS["recip"] + 1 + FLOPS["fbar_gamma_f"] + \
                 FLOPS["vscale_r"]
         else:
             self.emit_amp(node[1])
 
     def emit_jacc(self, amp_sym, colour):
+        # magnitude of the contribution, for the rounding-error estimate of the
+        # float32 form (|re| + |im| bounds |a| within sqrt 2)
+        self.w(f"    const T mag = TRACK ? fabs({amp_sym}.r) + fabs({amp_sym}.i) : T(0);")
         for order, c in sorted(colour.items()):
+            self.w(f"    if constexpr (TRACK) S[{self.kindex[order]}] += mag;")
             k = self.kindex[order]
             op = _coef_ops(c)
             if op == "add":
@@ -354,18 +405,18 @@ class GGEmitter:
             vt = self.osym(("vt",))
             # A = g dot(s3, VT) + (-i g^2) dot(s4, VT); VT carries g/Q_T^2
             if "s3" in parts and "s4" in parts:
-                self.w(f"    const cx<T> a = x.g * dot(s3, {vt}) + times_mi(x.g * x.g * dot(s4, {vt}));")
+                self.w(f"    const cx<T> a = x.gT * dot(s3, {vt}) + times_mi(x.gT * x.gT * dot(s4, {vt}));")
                 self.flops += 2 * FLOPS["dot_cc"] + 6
             elif "s3" in parts:
-                self.w(f"    const cx<T> a = x.g * dot(s3, {vt});")
+                self.w(f"    const cx<T> a = x.gT * dot(s3, {vt});")
                 self.flops += FLOPS["dot_cc"] + 2
             else:
-                self.w(f"    const cx<T> a = times_mi(x.g * x.g * dot(s4, {vt}));")
+                self.w(f"    const cx<T> a = times_mi(x.gT * x.gT * dot(s4, {vt}));")
                 self.flops += FLOPS["dot_cc"] + 3
         else:
             L = self.osym(("L", amp["L"]))
             R = self.osym(("R", amp["R"]))
-            self.w(f"    const cx<T> a = times_i(x.g * row_col(row_slash({L}, {self.cur(amp['W'])}), {R}));")
+            self.w(f"    const cx<T> a = times_i(x.gT * row_col(row_slash({L}, {self.cur(amp['W'])}), {R}));")
             self.flops += FLOPS["row_slash"] + FLOPS["row_col"] + 2
         self.emit_jacc("a", amp["colour"])
         self.w("}")
@@ -374,9 +425,11 @@ class GGEmitter:
         self.names = {}
         self.counter = 0
         self.mom_names = [f"q{a}" for a in range(self.n)] + ["p3", "p4"]
+        # the momenta are fenced in place (one copy, shared with the caller)
         for a in range(self.n):
-            self.w(f"mom4<T> q{a} = x.q[{a}];")
-        self.w("mom4<T> p3 = x.p3, p4 = x.p4;")
+            self.w(f"mom4<double>& q{a} = x.q[{a}];")
+        self.w("mom4<double>& p3 = x.p3;")
+        self.w("mom4<double>& p4 = x.p4;")
         ops = self.schedule(self.cap)
         self.n_ops = len(ops)
         for node in ops:
@@ -424,6 +477,16 @@ class GGEmitter:
         body = self.lines
         executed_flops = self.flops
         amp_flops = alg
+        # float32 program: wavefunctions take half the registers, so more of
+        # them stay alive and less is recomputed
+        keep_cap = self.cap
+        self.cap = self.cap_f32
+        self.lines = []
+        self.flops = 0
+        self.emit_amps()
+        body_f32 = self.lines
+        executed_flops_f32 = self.flops
+        self.cap = keep_cap
         ext_flops = FLOPS["eps"] * self.n + 2 * FLOPS["spinor"]
         n = self.n
         nc = len(self.perms)
@@ -450,9 +513,19 @@ class GGEmitter:
         h.append(f"    static constexpr int n_amplitudes = {st['amplitudes']};")
         h.append(f"    static constexpr int ndiag = {count_feynman_diagrams(n)};")
         h.append("")
-        h.append("    template <typename T>")
-        h.append("    static MEV void amps(const gg_ext<T, " + str(n) + ">& x, cx<T>* __restrict__ J) {")
+        h.append("    // TRACK: also accumulate S[k] = sum of |contribution| to J[k] (error estimate)")
+        h.append("    template <typename T, bool TRACK = false>")
+        h.append("    static MEV void amps(gg_ext<T, " + str(n) + ">& x, cx<T>* __restrict__ J, "
+                 "T* __restrict__ S = nullptr) {")
         h.extend(body)
+        h.append("    }")
+        h.append("")
+        h.append(f"    // the same program scheduled for float32 (live-set cap {self.cap_f32}; "
+                 f"{executed_flops_f32 + ext_flops} flops executed per helicity)")
+        h.append("    template <typename T, bool TRACK = false>")
+        h.append("    static MEV void amps_f32(gg_ext<T, " + str(n) + ">& x, cx<T>* __restrict__ J, "
+                 "T* __restrict__ S = nullptr) {")
+        h.extend(body_f32)
         h.append("    }")
         h.append("")
         h.append("    // J^dag N J with N = lcd * C (integer numerators, symmetric)")
@@ -461,9 +534,26 @@ class GGEmitter:
         h.extend(self.emit_colour())
         h.append("    }")
         h.append("")
-        h.append(f"    static constexpr int colour_num[{nc}][{nc}] = {{")
+        import numpy as np
+
+        N = np.array(self.num, dtype=float)
+        ev = np.linalg.eigvalsh(N)
+        abs_lmax = float(np.linalg.eigvalsh(np.abs(N)).max())
+        # a-priori relative error of J^dag N J when J is carried as float16 hi + lo
+        # (2^-22 per element) and the products accumulate in float32:
+        #   2 * 2^-22 * cond(N) + sqrt(ncol) * 2^-24 * lambda_max(|N|) / lambda_min(N)
+        col_err = float(2 * 2.0 ** -22 * ev.max() / ev.min() + math.sqrt(nc) * 2.0 ** -24 * abs_lmax / ev.min())
+        h.append(f"    static constexpr double abs_lambda_max = {abs_lmax!r};  // largest eigenvalue of |N|")
+        h.append(f"    static constexpr double lambda_min = {float(ev.min())!r};  // smallest eigenvalue of N")
+        h.append(f"    static constexpr double colour_err_f16 = {col_err!r};")
+        h.append("};")
+        h.append("")
+        h.append(f"// colour-matrix numerators for device-side lookup, row-major [{nc}][{nc}]")
+        h.append(f"__device__ __constant__ static const short colour_num_{self.name}[{nc * nc}] = {{")
         for row in self.num:
-            h.append("        {" + ", ".join(str(v) for v in row) + "},")
-        h.append("    };")
+            h.append("    " + ", ".join(str(v) for v in row) + ",")
+        h.append("};")
+        h.append(f"template <> struct colour_table<proc_{self.name}> {{")
+        h.append(f"    static MEV int get(int k, int l) {{ return colour_num_{self.name}[k * {nc} + l]; }}")
         h.append("};")
         return "\n".join(h) + "\n"

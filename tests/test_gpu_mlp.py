@@ -1,0 +1,201 @@
+"""The surrogate network's HIP kernels and the two-stage unweighting (MI355X).
+
+Forward and backward are compared with the float64 CPU reference run on the
+same BF16-rounded weights and inputs, rounding the activations (and, in the
+backward pass, the pre-activation gradients) to BF16 where the kernels store
+them; Adam is compared with its closed form; unweighting decisions with the
+CPU reference of the algorithm on the same uniforms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from inputs import process_points, uniforms
+from oracle import mlp_ref as R
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def me_mod(torch_cuda):
+    import paper_2503_21935_amd as me
+
+    me.lib()
+    return me
+
+
+def emulated_forward(theta, x, keep=False):
+    """Float64 forward with BF16 weights, inputs and stored activations."""
+    layers, w_out, b_out = R.unpack(theta)
+    h = R.bf16_round(x)
+    zs, hs = [], [h]
+    for W, b in layers:
+        z = h @ R.bf16_round(W).T + b
+        h = R.bf16_round(R.silu(z))
+        zs.append(z)
+        hs.append(h)
+    y = h @ w_out + b_out[0]
+    return (y, zs, hs) if keep else y
+
+
+def emulated_grad(theta, x, t):
+    y, zs, hs = emulated_forward(theta, x, keep=True)
+    layers, w_out, _ = R.unpack(theta)
+    m = len(t)
+    dy = 2 * (y - t) / m
+    g_layers = [None] * len(layers)
+    g_wout = hs[-1].T @ dy
+    g_bout = np.array([dy.sum()])
+    dz = R.bf16_round(np.outer(dy, w_out) * R.silu_prime(zs[-1]))
+    for l in range(len(layers) - 1, -1, -1):
+        g_layers[l] = (dz.T @ hs[l], dz.sum(axis=0))
+        if l > 0:
+            dz = R.bf16_round((dz @ R.bf16_round(layers[l][0])) * R.silu_prime(zs[l - 1]))
+    parts = []
+    for gW, gb in g_layers:
+        parts += [gW.ravel(), gb]
+    return np.concatenate(parts + [g_wout, g_bout])
+
+
+def features_np(mom):
+    s = (mom[:, 0, 0] + mom[:, 1, 0]) ** 2 - ((mom[:, 0, 1:] + mom[:, 1, 1:]) ** 2).sum(-1)
+    return (mom.reshape(len(mom), -1) / np.sqrt(s)[:, None]).astype(np.float32)
+
+
+def test_features(me_mod, torch_cuda):
+    torch = torch_cuda
+    mom = process_points("gg_ttgg", 1000, 4)
+    x = me_mod.features(torch.from_numpy(mom).cuda()).cpu().numpy()
+    np.testing.assert_allclose(x, features_np(mom), rtol=1e-7)
+
+
+def test_forward_matches_reference(me_mod, torch_cuda):
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=11)
+    theta = net.get_params().astype(np.float64)
+    x = features_np(process_points("gg_ttgg", 3000, 4))  # not a multiple of 64
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    emu = emulated_forward(theta, x.astype(np.float64))
+    exact = R.forward(theta, x.astype(np.float64))
+    rel_emu = np.linalg.norm(y - emu) / np.linalg.norm(emu)
+    rel_exact = np.linalg.norm(y - exact) / np.linalg.norm(exact)
+    print(f"[mlp] forward: vs BF16-emulating reference {rel_emu:.2e}, vs float64 {rel_exact:.2e}", flush=True)
+    assert rel_emu < 2e-3
+    assert rel_exact < 3e-2
+    net.close()
+
+
+def test_backward_matches_reference(me_mod, torch_cuda):
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=12)
+    theta = net.get_params().astype(np.float64)
+    x = features_np(process_points("gg_ttgg", 512, 5))
+    t = np.random.default_rng(3).normal(size=512).astype(np.float32)
+    g, loss = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    ge = emulated_grad(theta, x.astype(np.float64), t.astype(np.float64))
+    lref, gx = R.loss_and_grad(theta, x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss.item() / lref - 1) < 1e-2
+    # per parameter tensor, norm-wise
+    n_in, W = 24, 256
+    offs = [0]
+    for fi in (n_in, W, W, W):
+        offs += [offs[-1] + W * fi, offs[-1] + W * fi + W]
+    offs += [offs[-1] + W, offs[-1] + W + 1]
+    worst = 0.0
+    for a, b in zip(offs[:-1], offs[1:]):
+        rel = np.linalg.norm(g[a:b] - ge[a:b]) / max(np.linalg.norm(ge[a:b]), 1e-30)
+        rel_x = np.linalg.norm(g[a:b] - gx[a:b]) / max(np.linalg.norm(gx[a:b]), 1e-30)
+        worst = max(worst, rel)
+        assert rel < 1e-2, (a, b, rel)
+        assert rel_x < 5e-2, (a, b, rel_x)
+    print(f"[mlp] backward: worst tensor vs BF16-emulating reference {worst:.2e}", flush=True)
+    net.close()
+
+
+def test_adam_step(me_mod, torch_cuda):
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=13)
+    theta = net.get_params()
+    x = torch.from_numpy(features_np(process_points("gg_ttgg", 256, 6))).cuda()
+    t = torch.from_numpy(np.random.default_rng(4).normal(size=256).astype(np.float32)).cuda()
+    g, _ = net.backward(x, t)
+    g = g.cpu().numpy().astype(np.float64)
+    lr = 1e-3
+    net.train_step(x, t, None, lr)
+    torch.cuda.synchronize()
+    new = net.get_params().astype(np.float64)
+    want, _, _ = R.adam_step(theta.astype(np.float64), 0.0, 0.0, g, 1, lr)
+    np.testing.assert_allclose(new, want, rtol=0, atol=2e-6 * lr + 1e-7)
+    net.close()
+
+
+def test_training_learns_log_me2(me_mod, torch_cuda):
+    """A short training run on oracle-labelled gg -> t tbar g g points lowers the loss."""
+    torch = torch_cuda
+    n = 1 << 14
+    mom = process_points("gg_ttgg", n, 4)
+    lab = np.log(oracle.me2("gg_ttgg", mom))
+    mu, sig = lab.mean(), lab.std()
+    t = torch.from_numpy(((lab - mu) / sig).astype(np.float32)).cuda()
+    x = me_mod.features(torch.from_numpy(mom).cuda())
+    net = me_mod.Surrogate(seed=14)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(5)
+    first = None
+    for epoch in range(6):
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).cuda()
+        for b in range(0, n, 512):
+            net.train_step(x, t, perm[b:b + 512], 1e-3, loss)
+            if first is None:
+                torch.cuda.synchronize()
+                first = loss.item()
+    y = net.forward(x)
+    mse = torch.mean((y - t) ** 2).item()
+    print(f"[mlp] training: first batch loss {first:.3f}, after 6 epochs mse {mse:.3f}", flush=True)
+    assert mse < 0.5 * first
+    net.close()
+
+
+def test_unweighting_matches_reference(me_mod, torch_cuda):
+    torch = torch_cuda
+    n = 8192
+    mom, w_ps = process_points("gg_ttgg", n, 5, return_weight=True)
+    u = uniforms(n, 2, 55)
+    me2 = oracle.me2("gg_ttgg", mom)
+    lab = np.log(me2)
+    mu, sig = float(lab.mean()), float(lab.std())
+    ctx = me_mod.MatrixElement("gg_ttgg")
+    net = me_mod.Surrogate(seed=15)
+    tm = torch.from_numpy(mom).cuda()
+    y = net.forward(me_mod.features(tm)).cpu().numpy().astype(np.float64)
+    s = np.exp(sig * y + mu) * w_ps
+    w = me2 * w_ps
+    s_max = float(np.quantile(s, 0.7))
+    r_max = float(np.quantile(w / s, 0.7))
+    out_idx = torch.empty(n, dtype=torch.int32, device="cuda")
+    out_w = torch.empty(n, dtype=torch.float64, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+    me_mod.unweight_two_stage(ctx.ctx, net.h, tm, torch.from_numpy(w_ps).cuda(), n, torch.from_numpy(u).cuda(),
+                              mu, sig, s_max, r_max, out_idx, out_w, cnt)
+    torch.cuda.synchronize()
+    n1, n2 = cnt.cpu().numpy().tolist()
+    got_idx = out_idx[:n2].cpu().numpy()
+    got_w = out_w[:n2].cpu().numpy()
+    order = np.argsort(got_idx)
+    got_idx, got_w = got_idx[order], got_w[order]
+    acc1, acc2, wt = R.two_stage(s, w, u[:, 0], u[:, 1], s_max, r_max)
+    assert n1 == int(acc1.sum())
+    assert np.array_equal(got_idx, np.nonzero(acc2)[0])
+    np.testing.assert_allclose(got_w, wt[acc2], rtol=1e-9)
+    print(f"[unweight] {n} points: stage 1 kept {n1}, accepted {n2}", flush=True)
+    ctx.close()
+    net.close()
