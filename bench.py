@@ -76,6 +76,33 @@ def bench_fp64(m, mom, out, args, stream):
     return timed(lambda: m.eval(mom, out=out, stream=stream), args.steps, stream)
 
 
+def bench_process(me, proc, nevt, seed, steps, stream, check=8):
+    """Float64 throughput of another process at its own workload size, with a
+    few events checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from inputs import process_points
+
+    mom_np = process_points(proc, nevt, seed, precise=True)
+    mom = torch.from_numpy(mom_np).cuda()
+    m = me.MatrixElement(proc)
+    info = m.info()
+    out = torch.empty(nevt, dtype=torch.float64, device=mom.device)
+    m.eval(mom, out=out, stream=stream)
+    k_s, wall = timed(lambda: m.eval(mom, out=out, stream=stream), steps, stream)
+    res = out.cpu().numpy()
+    idx = np.sort(np.random.default_rng(5).choice(nevt, check, replace=False))
+    rel = np.abs(res[idx] / oracle.me2(proc, mom_np[idx]) - 1)
+    m.close()
+    achieved = info["flops_per_event"] * nevt / k_s / 1e12
+    return {"workload": f"{proc}, {nevt} RAMBO points seed {seed}", "MEs_per_s": nevt / wall,
+            "kernel_ms": k_s * 1e3, "flops_per_event": info["flops_per_event"],
+            "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / PEAK["fp64"],
+            "max_rel_dev_vs_oracle": float(rel.max()), "checked_events": check}
+
+
 def bench_mixed(me, m, mom, mom_np, args, stream):
     import numpy as np
     import torch
@@ -238,7 +265,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
     ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp64,mixed,surrogate")
+    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg",
+                    help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3)")
     ap.add_argument("--n-train", type=int, default=1 << 22)
     ap.add_argument("--n-calib", type=int, default=1 << 20)
     ap.add_argument("--n-unweight", type=int, default=1 << 22)
@@ -322,6 +350,10 @@ def main():
         del mom
         line["forms"]["surrogate"] = bench_surrogate(me, args, stream)
         log(f"surrogate: {line['forms']['surrogate']}")
+
+    if "gg_ttggg" in forms:
+        line["processes"] = {"gg_ttggg": bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream)}
+        log(f"gg_ttggg: {line['processes']['gg_ttggg']}")
 
     if not args.no_cpu:
         import oracle

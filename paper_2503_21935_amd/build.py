@@ -17,7 +17,10 @@ GEN = os.path.join(CSRC, "gen")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme.so")
 
-PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg"]
+PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"]
+
+# processes whose colour-flow amplitudes live in LDS (workgroup kernel of me_coop.h)
+COOP = {"gg_ttggg"}
 
 # Calibration of the mixed form's amplitude error estimate (multiplies
 # u32 * 2 lambda_max(|N|) |S| |J| / Q); fixed by comparing float32 results
@@ -57,6 +60,33 @@ static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, c
 extern const me_process_desc me_desc_{name} = {{
     "{name}", {kind}, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
     {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, {mixed_ptr}, {cest}, {colerr}}};
+#endif
+"""
+
+_TU_COOP = """// Generated translation unit: kernels of {name} (workgroup form, J in LDS).
+#include "me_coop.h"
+{include}
+
+static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                             const me_params& prm, double* qhel, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_TILE - 1) / ME_TILE));
+    hipLaunchKernelGGL((k_me_gg_coop<{proc}>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out, hels,
+                       nh, prm, qhel, nullptr, nullptr);
+    return hipGetLastError();
+}}
+
+static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                 const me_params& prm, const int* idx, const int* count, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_TILE - 1) / ME_TILE));
+    hipLaunchKernelGGL((k_me_gg_coop<{proc}>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out, hels,
+                       nh, prm, nullptr, idx, count);
+    return hipGetLastError();
+}}
+
+#ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
+extern const me_process_desc me_desc_{name} = {{
+    "{name}", ME_KIND_GG, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
+    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, nullptr, 0.0, 0.0}};
 #endif
 """
 
@@ -107,6 +137,10 @@ def generate_sources(processes):
             inc, kernel, proc, kind = f'#include "gen/proc_{name}.h"', "k_me_gg", f"proc_{name}", "ME_KIND_GG"
             mixed, mixed_ptr, colerr = _MIXED.format(proc=proc), "launch_mixed", f"{proc}::colour_err_f16"
         path = os.path.join(GEN, f"tu_{name}.hip")
+        if name in COOP:
+            _write(path, _TU_COOP.format(name=name, include=inc, proc=proc))
+            tus.append(path)
+            continue
         _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind, mixed=mixed,
                                 mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr))
         tus.append(path)

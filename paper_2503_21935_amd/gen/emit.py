@@ -306,6 +306,10 @@ class GGEmitter:
                     self.flops += FLOPS["vadd"]
         return parts
 
+    def emit_momenta(self, used):
+        """Make the momenta a node reads opaque (fenced in place)."""
+        self.w("fence(" + ", ".join(used) + ");")
+
     def emit_node(self, node):
         kind = node[0]
         # New SSA names for the momenta this node reads: helicity-independent
@@ -313,7 +317,7 @@ class GGEmitter:
         # where needed instead of being merged into long-lived registers.
         used = self.node_momenta(node)
         if used:
-            self.w("fence(" + ", ".join(used) + ");")
+            self.emit_momenta(used)
         if kind == "c":
             c = self.plan.currents[node[1]]
             self.w(f"// gluon current over {sorted(c.leaves)} ({len(c.terms)} vertex terms)")

@@ -28,6 +28,9 @@ SMALL = [
     ("gg_tt", 65536, 1),
     ("gg_ttg", 4096, 7),
     ("gg_ttgg", 4096, 2),
+    # the oracle takes about a second per g g -> t tbar g g g event: two tiles of
+    # the workgroup kernel, the second one ragged
+    ("gg_ttggg", 80, 3),
 ]
 
 
@@ -100,7 +103,8 @@ def test_parity_small(me_mod, torch_cuda, proc, n, seed):
     print(f"[parity] {proc}: max rel {rel.max():.2e}, median {np.median(rel):.2e}", flush=True)
 
 
-@pytest.mark.parametrize("proc,n", [("gg_tt", 3), ("gg_ttg", 65), ("gg_ttgg", 127), ("ee_mumu", 1)])
+@pytest.mark.parametrize("proc,n", [("gg_tt", 3), ("gg_ttg", 65), ("gg_ttgg", 127), ("ee_mumu", 1),
+                                    ("gg_ttggg", 1), ("gg_ttggg", 65)])
 def test_ragged_sizes(me_mod, torch_cuda, proc, n):
     """Sizes that leave a partial last block (64 lanes per block)."""
     mom = process_points(proc, n, 123)
@@ -108,11 +112,11 @@ def test_ragged_sizes(me_mod, torch_cuda, proc, n):
     check_parity(proc, mom, got)
 
 
-@pytest.mark.parametrize("proc", ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg"])
+@pytest.mark.parametrize("proc", ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"])
 def test_per_helicity(me_mod, torch_cuda, proc):
     """Each helicity's J^dag C J agrees with the oracle's (phase conventions cancel)."""
     torch = torch_cuda
-    mom = process_points(proc, 64, 31)
+    mom = process_points(proc, 8 if proc == "gg_ttggg" else 64, 31)
     m = get_me(me_mod, proc)
     me2, qh = m.eval_helicities(torch.from_numpy(mom).cuda())
     torch.cuda.synchronize()
@@ -123,7 +127,8 @@ def test_per_helicity(me_mod, torch_cuda, proc):
     np.testing.assert_allclose(me2, want_me2, rtol=1e-12)
 
 
-@pytest.mark.parametrize("proc,expect", [("ee_mumu", 4), ("gg_tt", 16), ("gg_ttg", 32), ("gg_ttgg", 64)])
+@pytest.mark.parametrize("proc,expect", [("ee_mumu", 4), ("gg_tt", 16), ("gg_ttg", 32), ("gg_ttgg", 64),
+                                         ("gg_ttggg", 128)])
 def test_helicity_filter(me_mod, torch_cuda, proc, expect):
     """The filter keeps exactly the helicities that contribute, and dropping the
     others changes nothing on fresh points."""
@@ -153,6 +158,20 @@ def test_full_size_sampled_ggttgg(me_mod, torch_cuda):
     idx = np.sort(np.random.default_rng(0).choice(n, 512, replace=False))
     idx = np.concatenate([idx, [0, n - 1]])
     check_parity("gg_ttgg", mom[idx], got[idx])
+
+
+def test_full_size_sampled_ggttggg(me_mod, torch_cuda):
+    """2^18 g g -> t tbar g g g points (seed 3) in one launch of the workgroup
+    kernel; a seeded sample of events is checked against the oracle."""
+    torch = torch_cuda
+    n = 1 << 18
+    mom = process_points("gg_ttggg", n, 3)
+    got = gpu_me2(me_mod, torch, "gg_ttggg", mom)
+    assert np.all(np.isfinite(got)) and np.all(got > 0)
+    idx = np.sort(np.random.default_rng(0).choice(n, 30, replace=False))
+    idx = np.concatenate([idx, [0, n - 1]])
+    rel = check_parity("gg_ttggg", mom[idx], got[idx])
+    print(f"[parity] gg_ttggg 2^18 sampled: max rel {rel.max():.2e}", flush=True)
 
 
 def test_full_size_ggtt(me_mod, torch_cuda):

@@ -88,3 +88,85 @@ def test_generated_flop_counts_positive():
     e = GGEmitter("gg_ttgg", 4, True, 6)
     e.render()
     assert e.algorithmic_flops() > 10000
+
+
+@pytest.fixture(scope="module")
+def coop5():
+    from paper_2503_21935_amd.gen.coop import GGCoopEmitter
+
+    return GGCoopEmitter("gg_ttggg", 5, True, cap=12, window=16, waves=4)
+
+
+def test_workgroup_program_covers_every_amplitude_once(coop5):
+    """The waves' relabelled copies of the representatives give every amplitude
+    of g g -> t tbar g g g with total weight exactly 1."""
+    e = coop5
+    tables = e._relabel_tables()
+    total = np.zeros(len(e.plan.amps))
+    for i in e.reps:
+        for pi in e.group:
+            total[e.relabel_amp(i, pi, tables)] += e.weight[i]
+    assert np.array_equal(total, np.ones(len(e.plan.amps)))
+    assert len(e.reps) == 243
+
+
+def test_workgroup_relabelled_colour_is_consistent(coop5):
+    """Relabelling a representative's colour expansion gives the colour of the
+    amplitude it maps to, up to one unit phase (absorbed by the Lorentz value)."""
+    e = coop5
+    tables = e._relabel_tables()
+    for i in e.reps:
+        for pi in e.group:
+            j = e.relabel_amp(i, pi, tables)
+            mine = {tuple(pi[a] for a in o): v for o, v in e.plan.amps[i]["colour"].items()}
+            theirs = e.plan.amps[j]["colour"]
+            assert set(mine) == set(theirs)
+            ratios = {complex(theirs[k] / mine[k]) for k in mine}
+            assert len({(round(r.real, 12), round(r.imag, 12)) for r in ratios}) == 1
+            assert abs(abs(next(iter(ratios))) - 1) < 1e-12
+
+
+def test_workgroup_flow_maps(coop5):
+    fm = coop5.flow_maps()
+    assert fm[0] == list(range(120))
+    for row in fm:
+        assert sorted(row) == list(range(120))
+
+
+def test_register_window_replays_to_direct_sums(coop5):
+    """Replaying the window actions (fill / hit / flush / direct) on random
+    amplitude values gives the same J as adding every contribution directly."""
+    from paper_2503_21935_amd.gen.emit import _coef_ops
+
+    e = coop5
+    rng = np.random.default_rng(0)
+    order = list(range(len(e.plan.amps)))
+    rng.shuffle(order)
+    for window in (4, 16):
+        e.window = window
+        acts, live = e.plan_window(order)
+        vals = rng.normal(size=len(e.plan.amps)) + 1j * rng.normal(size=len(e.plan.amps))
+        direct = np.zeros(120, complex)
+        J = np.zeros(120, complex)
+        slots = {}
+        for t, i in enumerate(order):
+            for (o, c), act in zip(sorted(e.plan.amps[i]["colour"].items()), acts[t]):
+                k = e.kindex[o]
+                v = complex(c) * vals[i]
+                direct[k] += v
+                if act[0] == "hit":
+                    slots[act[1]] = (slots[act[1]][0], slots[act[1]][1] + v)
+                    assert slots[act[1]][0] == k
+                elif act[0] == "fill":
+                    if act[2] is not None:
+                        old_k, old_v = slots[act[1]]
+                        assert old_k == act[2]
+                        J[old_k] += old_v
+                    slots[act[1]] = (k, v)
+                else:
+                    J[k] += v
+        for s, (k, v) in slots.items():
+            assert live[k] == s
+            J[k] += v
+        np.testing.assert_allclose(J, direct, atol=1e-12)
+    e.window = 16
