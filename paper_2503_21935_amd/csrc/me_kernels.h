@@ -35,22 +35,21 @@ MEV void load_event(const double* __restrict__ mom, int64_t ev, mom4<T>* p) {
     }
 }
 
-// qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
-// filter and for tests; entries of helicities not in the list are untouched.
 // Wavefunctions of one helicity in the amplitude type T (built in float64
-// from the momenta held in x: incoming gluons p = q, outgoing p = -q).
+// from the momenta in LDS: incoming gluons p = q, outgoing p = -q).
 template <class P, typename T>
 MEV void gg_externals(gg_ext<T, P::ngluon>& x, int h) {
     constexpr int NP = P::npart, NG = P::ngluon;
 #pragma unroll
     for (int a = 0; a < NG; ++a) {
         const int ip = (a < 2) ? a : a + 2;
-        const vec4<double> e = gluon_eps((a < 2) ? x.q[a] : -x.q[a], helicity_of<NP>(h, ip), a >= 2);
+        const mom4<double> q = mom_ld(x, a);
+        const vec4<double> e = gluon_eps((a < 2) ? q : -q, helicity_of<NP>(h, ip), a >= 2);
 #pragma unroll
         for (int c = 0; c < 4; ++c) x.eps[a].v[c] = to_t<T>(e.v[c]);
     }
-    const spinor<double> u = bar(u_spinor(x.p3, x.m, helicity_of<NP>(h, 2)));
-    const spinor<double> v = v_spinor(x.p4, x.m, helicity_of<NP>(h, 3));
+    const spinor<double> u = bar(u_spinor(mom_ld(x, NG), x.m, helicity_of<NP>(h, 2)));
+    const spinor<double> v = v_spinor(mom_ld(x, NG + 1), x.m, helicity_of<NP>(h, 3));
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
         x.ubar3.s[c] = to_t<T>(u.s[c]);
@@ -58,25 +57,30 @@ MEV void gg_externals(gg_ext<T, P::ngluon>& x, int h) {
     }
 }
 
+// Writes this lane's event into its column of the block's momentum tile Qt
+// (slots as described at gg_ext) and points x at it.  Each lane reads back
+// only its own column, which the same wave wrote before: no barrier needed.
 template <class P, typename T>
-MEV void gg_opaque(gg_ext<T, P::ngluon>& x) {
+MEV void gg_setup(gg_ext<T, P::ngluon>& x, const double* __restrict__ mom, int64_t ev, double* Qt, int lane,
+                  const me_params& prm) {
+    constexpr int NP = P::npart, NG = P::ngluon;
+    const double2* pe = reinterpret_cast<const double2*>(mom + ev * (NP * 4));
 #pragma unroll
-    for (int a = 0; a < P::ngluon; ++a) opaque_mom(x.q[a]);
-    opaque_mom(x.p3);
-    opaque_mom(x.p4);
-}
-
-template <class P, typename T>
-MEV void gg_setup(gg_ext<T, P::ngluon>& x, const mom4<double>* p, const me_params& prm) {
+    for (int r = 0; r < NG + 2; ++r) {
+        const int ip = (r < 2) ? r : (r < NG) ? r + 2 : r - NG + 2;
+        const double sg = (r >= 2 && r < NG) ? -1.0 : 1.0;
+        const double2 a = pe[2 * ip], b = pe[2 * ip + 1];
+        Qt[ME_MOM_ROW(r) + 0 * 64 + lane] = sg * a.x;
+        Qt[ME_MOM_ROW(r) + 1 * 64 + lane] = sg * a.y;
+        Qt[ME_MOM_ROW(r) + 2 * 64 + lane] = sg * b.x;
+        Qt[ME_MOM_ROW(r) + 3 * 64 + lane] = sg * b.y;
+    }
+    x.Q = (lds_cdouble*)(Qt + lane);
     x.m = prm.mt;
     x.mw = prm.mt * prm.wt;
     x.g = prm.gs;
     x.mT = T(prm.mt);
     x.gT = T(prm.gs);
-    x.p3 = p[2];
-    x.p4 = p[3];
-#pragma unroll
-    for (int a = 0; a < P::ngluon; ++a) x.q[a] = (a < 2) ? p[a] : -p[a + 2];
 }
 
 // qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
@@ -96,19 +100,18 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ m
         return;
     }
     using T = double;
-    constexpr int NP = P::npart, NG = P::ngluon;
-    mom4<double> p[NP];
-    load_event<double, NP>(mom, ev, p);
+    constexpr int NG = P::ngluon;
+    static_assert(ME_BLOCK == 64, "one wave per block");
+    __shared__ double Qt[ME_MOM_ROW(NG + 2)];
     gg_ext<T, NG> x;
-    gg_setup<P, T>(x, p, prm);
+    gg_setup<P, T>(x, mom, ev, Qt, threadIdx.x, prm);
     T acc = T(0);
 #pragma unroll 1
     for (int ih = 0; ih < nh; ++ih) {
         const int h = hels[ih];
-        // Opaque momenta in every iteration: the helicity-independent
-        // subexpressions are recomputed per helicity instead of being hoisted
-        // out of the loop, where they would occupy registers throughout.
-        gg_opaque<P, T>(x);
+        // The momenta are read from LDS where they are used: the
+        // helicity-independent subexpressions are recomputed per helicity
+        // instead of being hoisted out of the loop into registers.
         gg_externals<P, T>(x, h);
         cx<T> J[P::ncol];
 #pragma unroll

@@ -4,7 +4,7 @@
 // at Jl[2k*64] and Jl[(2k+1)*64] with Jl pointing at the lane's column, so a
 // wave touches 64 consecutive elements per access (no bank conflicts).
 #pragma once
-#include "me_vertex.h"
+#include "me_process.h"
 
 // J_k += v (atomic: several waves add into the same J_k)
 template <typename T>
@@ -29,9 +29,6 @@ MEV int fmap_at(int t0, int t1) {
 }
 
 MEV void opaque_int(int& a, int& b) { asm volatile("" : "+v"(a), "+v"(b)); }
-
-// Pointer into LDS (address space 3): reads compile to ds_read.
-typedef __attribute__((address_space(3))) const double lds_cdouble;
 
 // External wavefunctions and constants of the workgroup program.  The
 // momenta are not held here: the tile keeps them in LDS as

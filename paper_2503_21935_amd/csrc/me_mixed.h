@@ -162,16 +162,14 @@ __global__ __launch_bounds__(ME_BLOCK, ME_MIXED_WAVES) void k_me_gg_mixed(const 
     const bool valid = ev < nevt;
     if (!valid) ev = nevt - 1;  // every lane takes part in the wave-wide colour GEMM
     using T = float;
-    constexpr int NP = P::npart, NG = P::ngluon;
-    mom4<double> p[NP];
-    load_event<double, NP>(mom, ev, p);
+    constexpr int NG = P::ngluon;
+    __shared__ double Qt[ME_MOM_ROW(NG + 2)];
     gg_ext<T, NG> x;
-    gg_setup<P, T>(x, p, prm);
+    gg_setup<P, T>(x, mom, ev, Qt, lane, prm);
     float acc = 0.f, dacc = 0.f;
 #pragma unroll 1
     for (int ih = 0; ih < nh; ++ih) {
         const int h = hels[ih];
-        gg_opaque<P, T>(x);
         gg_externals<P, T>(x, h);
         cx<T> J[P::ncol];
         T S[P::ncol];

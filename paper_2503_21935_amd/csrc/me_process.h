@@ -16,9 +16,19 @@ struct me_params {
 template <class P>
 struct colour_table;
 
-// External wavefunctions and momenta of one event at one helicity for
-// g g -> t tbar + (NG-2) g.  Gluon momenta are counted as flowing into the
-// diagram (q = p for the two incoming gluons, q = -p for outgoing ones).
+// Pointer into LDS (address space 3): reads compile to ds_read.
+typedef __attribute__((address_space(3))) const double lds_cdouble;
+
+// Row offset (in doubles) of momentum slot j in a 64-lane tile of momenta
+// held in LDS as [slot][component][lane].
+#define ME_MOM_ROW(j) (4 * 64 * (j))
+
+// External wavefunctions of one event at one helicity for
+// g g -> t tbar + (NG-2) g, and where its momenta are.  The momenta are kept
+// in LDS, slots 0..NG-1 for the gluons counted as flowing into the diagram
+// (q = p for the two incoming gluons, q = -p for outgoing ones), slot NG for
+// p3 and NG+1 for p4, and read afresh where a node needs them (mom_ld), so
+// that no helicity-independent value occupies registers across the program.
 // Momenta, propagator denominators and couplings stay in float64 for every
 // amplitude type T: the near-on-shell propagators cancel p^2 against m^2,
 // which float32 cannot resolve.
@@ -26,11 +36,19 @@ template <typename T, int NG>
 struct gg_ext {
     vec4<T> eps[NG];
     spinor<T> ubar3, v4;
-    mom4<double> q[NG];
-    mom4<double> p3, p4;
+    lds_cdouble* Q;   // this lane's column of the tile's momenta
     double m, mw, g;  // top mass, mass * width, strong coupling
     T mT, gT;         // the same in the amplitude type
 };
+
+// Momentum of slot j, read from LDS through an address the compiler cannot
+// see through: no read is merged with another or moved out of its node.
+template <typename T, int NG>
+MEV mom4<double> mom_ld(const gg_ext<T, NG>& x, int j) {
+    lds_cdouble* a = x.Q + ME_MOM_ROW(j);
+    asm volatile("" : "+v"(a));
+    return mom4<double>{a[0], a[64], a[128], a[192]};
+}
 
 // e+(p1) e-(p2) -> mu+(p3) mu-(p4) through an s-channel photon and Z:
 //   M = (eQ)^2 (Je.Jm)/s + gz^2 [Je'.Jm' - (Je'.k)(Jm'.k)/MZ^2] / (s - MZ^2 + i MZ WZ),

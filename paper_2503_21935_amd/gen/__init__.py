@@ -13,13 +13,13 @@ from .emit import GGEmitter
 
 GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # Maximum number of wavefunctions kept alive at once by the emitted program
-# (more are recomputed).  Chosen per process by compiling and counting
-# float64 operations plus VGPR<->AGPR moves (both take a VALU issue slot):
-# g g -> t tbar g g is cheapest at 10 without scratch spills (12 and above
-# spill); the float32 program fits without any recomputation.  For
-# g g -> t tbar g g g (workgroup program, no J in registers) 8 with a window of
-# 16 leaves the least private memory.
-LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 10, "gg_ttggg": 8}
+# (more are recomputed).  The momenta live in LDS, so the register budget
+# goes to wavefunctions and J.  Chosen per process by compiling and timing:
+# g g -> t tbar g g runs fastest at 14 (49.5 ms per 2^20 events against
+# 50.5 ms at 12, which has no private memory at all, and 44 bytes of it per
+# lane at 14); for g g -> t tbar g g g (workgroup program, J in LDS) 8 with a
+# window of 16 leaves no private memory.
+LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14, "gg_ttggg": 8}
 LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 # Processes whose colour-flow amplitudes are kept in LDS by a workgroup of
 # waves sharing one program (see coop.py): register window of J per wave.

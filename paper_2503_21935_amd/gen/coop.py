@@ -278,14 +278,6 @@ class GGCoopEmitter(GGEmitter):
                 self.w(f"    lds_acc(Jl, fmap_at<{k}>(fm0, fm1), {val});")
                 self.flops += FLOPS["jacc"]
 
-    def emit_momenta(self, used):
-        if not self.coop:
-            return super().emit_momenta(used)
-        # fresh volatile LDS reads: nothing helicity-independent stays in registers
-        slot = {f"q{a}": a for a in range(self.n)}
-        slot.update(p3=self.n, p4=self.n + 1)
-        self.w(" ".join(f"{nm} = mom_ld(x, {slot[nm]});" for nm in used))
-
     def emit_program(self, cap):
         full = self.plan.amps
         self.plan.amps = [full[i] for i in self.reps]

@@ -307,8 +307,12 @@ class GGEmitter:
         return parts
 
     def emit_momenta(self, used):
-        """Make the momenta a node reads opaque (fenced in place)."""
-        self.w("fence(" + ", ".join(used) + ");")
+        """Fresh reads of the momenta a node uses from the tile in LDS (slots:
+        gluons 0..n-1, then p3, p4): nothing helicity-independent stays in
+        registers between nodes."""
+        slot = {f"q{a}": a for a in range(self.n)}
+        slot.update(p3=self.n, p4=self.n + 1)
+        self.w(" ".join(f"{nm} = mom_ld(x, {slot[nm]});" for nm in used))
 
     def emit_node(self, node):
         kind = node[0]
@@ -429,11 +433,8 @@ class GGEmitter:
         self.names = {}
         self.counter = 0
         self.mom_names = [f"q{a}" for a in range(self.n)] + ["p3", "p4"]
-        # the momenta are fenced in place (one copy, shared with the caller)
-        for a in range(self.n):
-            self.w(f"mom4<double>& q{a} = x.q[{a}];")
-        self.w("mom4<double>& p3 = x.p3;")
-        self.w("mom4<double>& p4 = x.p4;")
+        # momenta: read from LDS by each node that uses them
+        self.w("mom4<double> " + ", ".join([f"q{a}" for a in range(self.n)] + ["p3", "p4"]) + ";")
         ops = self.schedule(self.cap)
         self.n_ops = len(ops)
         for node in ops:
