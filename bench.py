@@ -51,7 +51,8 @@ def kernel_sources_digest(process):
     """Digest of the sources that make up the float64 kernel of `process`."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_21935_amd", "csrc")
-    for f in ("me_vertex.h", "me_process.h", "me_kernels.h", "me_launch.h", os.path.join("gen", f"proc_{process}.h")):
+    for f in ("me_vertex.h", "me_process.h", "me_kernels.h", "me_launch.h", "me_lds.h", "me_coop.h",
+              os.path.join("gen", f"proc_{process}.h")):
         p = os.path.join(csrc, f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -97,7 +98,9 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8):
     rel = np.abs(res[idx] / oracle.me2(proc, mom_np[idx]) - 1)
     m.close()
     achieved = info["flops_per_event"] * nevt / k_s / 1e12
-    return {"workload": f"{proc}, {nevt} RAMBO points seed {seed}", "MEs_per_s": nevt / wall,
+    kernel = f"k_me_gg_coop<proc_{proc}>" if proc == "gg_ttggg" else f"k_me_gg<proc_{proc}>"
+    return {"workload": f"{proc}, {nevt} RAMBO points seed {seed}", "MEs_per_s": nevt / wall, "kernel": kernel,
+            "traffic": traffic_from_profile(proc, kernel),
             "kernel_ms": k_s * 1e3, "flops_per_event": info["flops_per_event"],
             "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / PEAK["fp64"],
             "max_rel_dev_vs_oracle": float(rel.max()), "checked_events": check}
