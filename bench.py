@@ -77,7 +77,7 @@ def bench_fp64(m, mom, out, args, stream):
     return timed(lambda: m.eval(mom, out=out, stream=stream), args.steps, stream)
 
 
-def bench_process(me, proc, nevt, seed, steps, stream, check=8):
+def bench_process(me, proc, nevt, seed, steps, stream, check=8, tol=None):
     """Float64 throughput of another process at its own workload size, with a
     few events checked against the oracle."""
     import numpy as np
@@ -95,7 +95,18 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8):
     k_s, wall = timed(lambda: m.eval(mom, out=out, stream=stream), steps, stream)
     res = out.cpu().numpy()
     idx = np.sort(np.random.default_rng(5).choice(nevt, check, replace=False))
-    rel = np.abs(res[idx] / oracle.me2(proc, mom_np[idx]) - 1)
+    ref = oracle.me2(proc, mom_np[idx])
+    rel = np.abs(res[idx] / ref - 1)
+    mixed = None
+    if m.info()["ncol"] > 1 and tol:
+        m.set_precision(me.ME_MIXED, tol)
+        m.eval(mom, out=out, stream=stream)
+        mk_s, mwall = timed(lambda: m.eval(mom, out=out, stream=stream), steps, stream)
+        nfb = m.fallback_count()
+        mres = out.cpu().numpy()
+        mixed = {"MEs_per_s": nevt / mwall, "ms_per_step": mwall * 1e3, "tolerance": tol,
+                 "fallback_fraction": nfb / nevt, "max_rel_err_vs_oracle": float(np.abs(mres[idx] / ref - 1).max())}
+        m.set_precision(me.ME_FP64, tol)
     m.close()
     achieved = info["flops_per_event"] * nevt / k_s / 1e12
     kernel = f"k_me_gg_coop<proc_{proc}>" if proc == "gg_ttggg" else f"k_me_gg<proc_{proc}>"
@@ -103,7 +114,7 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8):
             "traffic": traffic_from_profile(proc, kernel),
             "kernel_ms": k_s * 1e3, "flops_per_event": info["flops_per_event"],
             "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / PEAK["fp64"],
-            "max_rel_dev_vs_oracle": float(rel.max()), "checked_events": check}
+            "max_rel_dev_vs_oracle": float(rel.max()), "checked_events": check, "mixed": mixed}
 
 
 def bench_mixed(me, m, mom, mom_np, args, stream):
@@ -355,7 +366,8 @@ def main():
         log(f"surrogate: {line['forms']['surrogate']}")
 
     if "gg_ttggg" in forms:
-        line["processes"] = {"gg_ttggg": bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream)}
+        line["processes"] = {"gg_ttggg": bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream,
+                                                       tol=args.tol if "mixed" in forms else None)}
         log(f"gg_ttggg: {line['processes']['gg_ttggg']}")
 
     if not args.no_cpu:

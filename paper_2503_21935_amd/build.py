@@ -84,10 +84,30 @@ static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, c
 }}
 
 #ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
+// the mixed-precision launcher is compiled in a translation unit of its own
+hipError_t me_launch_mixed_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                  const me_params& prm, float tol, float cest, int* flag_count, int* flag_idx,
+                                  float* err_out, unsigned char* flag_out, hipStream_t s);
 extern const me_process_desc me_desc_{name} = {{
     "{name}", ME_KIND_GG, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
-    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, nullptr, 0.0, 0.0}};
+    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, me_launch_mixed_{name}, {cest},
+    {proc}::colour_err_f16}};
 #endif
+"""
+
+_TU_COOP_MIXED = """// Generated translation unit: mixed-precision kernel of {name} (workgroup form).
+#include "me_coop_mixed.h"
+{include}
+
+hipError_t me_launch_mixed_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                  const me_params& prm, float tol, float cest, int* flag_count, int* flag_idx,
+                                  float* err_out, unsigned char* flag_out, hipStream_t s) {{
+    if (flag_count) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, flag_count);
+    const dim3 grid((unsigned)((nevt + ME_TILE - 1) / ME_TILE));
+    hipLaunchKernelGGL((k_me_gg_coop_mixed<{proc}>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out,
+                       hels, nh, prm, tol, cest, flag_count, flag_idx, err_out, flag_out);
+    return hipGetLastError();
+}}
 """
 
 _MIXED = """
@@ -138,8 +158,11 @@ def generate_sources(processes):
             mixed, mixed_ptr, colerr = _MIXED.format(proc=proc), "launch_mixed", f"{proc}::colour_err_f16"
         path = os.path.join(GEN, f"tu_{name}.hip")
         if name in COOP:
-            _write(path, _TU_COOP.format(name=name, include=inc, proc=proc))
+            _write(path, _TU_COOP.format(name=name, include=inc, proc=proc, cest=MIXED_CEST.get(name, 8.0)))
             tus.append(path)
+            path_m = os.path.join(GEN, f"tu_{name}_mixed.hip")
+            _write(path_m, _TU_COOP_MIXED.format(name=name, include=inc, proc=proc))
+            tus.append(path_m)
             continue
         _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind, mixed=mixed,
                                 mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr))

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(ME_TILE * P::waves, 1) void k_me_gg_coop(
         for (int e = threadIdx.x; e < P::ncol * 2 * ME_TILE; e += ME_TILE * P::waves) Jt[e] = 0.0;
         __syncthreads();
         coop_externals<P, double>(x, h, wave);
-        P::template amps_wave<double>(x, Jl, fm0, fm1, wsel);
+        P::template amps_wave<double>(x, Jl, nullptr, fm0, fm1, wsel);
         __syncthreads();
         const double q = coop_colour<P, 0>(wave, Jl);
         acc += q;

@@ -13,6 +13,12 @@ MEV void lds_acc(T* __restrict__ Jl, int k, const cx<T>& v) {
     atomicAdd(Jl + (2 * k + 1) * 64, v.i);
 }
 
+// S_k += v (magnitude sums of the float32 form, [k][lane])
+template <typename T>
+MEV void lds_acc_s(T* __restrict__ Sl, int k, T v) {
+    atomicAdd(Sl + k * 64, v);
+}
+
 template <typename T>
 MEV cx<T> lds_get(const T* __restrict__ Jl, int k) {
     return mk(Jl[(2 * k) * 64], Jl[(2 * k + 1) * 64]);

@@ -255,6 +255,8 @@ class GGCoopEmitter(GGEmitter):
             self.w(f"    const cx<T> aw = T({wt!r}) * {amp_sym};  // amplitude fixed by part of the group")
             self.flops += 2
             src = "aw"
+        # magnitude of the contribution for the float32 form's error estimate
+        self.w(f"    const T mag = TRACK ? fabs({src}.r) + fabs({src}.i) : T(0);")
         for (order, c), act in zip(sorted(colour.items()), acts):
             k = self.kindex[order]
             op = _coef_ops(c)
@@ -267,15 +269,19 @@ class GGCoopEmitter(GGEmitter):
                     self.w(f"    jw{s} -= {src};")
                 else:
                     self.w(f"    jw{s} += {val};")
+                self.w(f"    if constexpr (TRACK) sw{s} += mag;")
                 self.flops += FLOPS["jacc"]
             elif act[0] == "fill":
                 s, v = act[1], act[2]
                 if v is not None:
                     self.w(f"    lds_acc(Jl, fmap_at<{v}>(fm0, fm1), jw{s});")
+                    self.w(f"    if constexpr (TRACK) lds_acc_s(Sl, fmap_at<{v}>(fm0, fm1), sw{s});")
                     self.flops += FLOPS["jacc"]
                 self.w(f"    jw{s} = {val};")
+                self.w(f"    if constexpr (TRACK) sw{s} = mag;")
             else:
                 self.w(f"    lds_acc(Jl, fmap_at<{k}>(fm0, fm1), {val});")
+                self.w(f"    if constexpr (TRACK) lds_acc_s(Sl, fmap_at<{k}>(fm0, fm1), mag);")
                 self.flops += FLOPS["jacc"]
 
     def emit_program(self, cap):
@@ -293,6 +299,7 @@ class GGCoopEmitter(GGEmitter):
             self._weights = [weights[i] for i in order]
             self._amp_pos = 0
             self.w("cx<T> " + ", ".join(f"jw{s}" for s in range(self.window)) + ";")
+            self.w("T " + ", ".join(f"sw{s}" for s in range(self.window)) + ";")
             for node in ops:
                 self.emit_node(node)
         finally:
@@ -300,6 +307,7 @@ class GGCoopEmitter(GGEmitter):
             self.plan.amps = full
         for f, s in sorted(live.items()):
             self.w(f"lds_acc(Jl, fmap_at<{f}>(fm0, fm1), jw{s});")
+            self.w(f"if constexpr (TRACK) lds_acc_s(Sl, fmap_at<{f}>(fm0, fm1), sw{s});")
             self.flops += FLOPS["jacc"]
         return self.lines, self.flops
 
@@ -419,8 +427,9 @@ class GGCoopEmitter(GGEmitter):
         h.append("    // lane k of fm0 (k < 64) or lane k - 64 of fm1.  wsel: the")
         h.append("    // wave index, held in a vector register so that the per-wave choices of the")
         h.append("    // propagator momentum are selects, not branches.")
-        h.append("    template <typename T>")
-        h.append(f"    static MEV void amps_wave(coop_ext<T, {n}>& x, T* __restrict__ Jl, "
+        h.append("    // TRACK: also add |contribution| into S (Sl = this lane's column of S[k][lane]).")
+        h.append("    template <typename T, bool TRACK = false>")
+        h.append(f"    static MEV void amps_wave(coop_ext<T, {n}>& x, T* __restrict__ Jl, T* __restrict__ Sl, "
                  "int fm0, int fm1, const int wsel) {")
         h.extend("        " + line[4:] for line in body)
         h.append("    }")
@@ -435,6 +444,37 @@ class GGCoopEmitter(GGEmitter):
             h.extend("            " + line for line in self.emit_colour_part(cassign[p], blocks))
         h.append("        }")
         h.append("    }")
+        import numpy as np
+
+        Nm = np.array(self.num, dtype=float)
+        ev = np.linalg.eigvalsh(Nm)
+        abs_lmax = float(np.linalg.eigvalsh(np.abs(Nm)).max())
+        col_err = float(2 * 2.0 ** -22 * ev.max() / ev.min() + math.sqrt(nc) * 2.0 ** -24 * abs_lmax / ev.min())
+        h.append(f"    static constexpr double abs_lambda_max = {abs_lmax!r};  // largest eigenvalue of |N|")
+        h.append(f"    static constexpr double lambda_min = {float(ev.min())!r};  // smallest eigenvalue of N")
+        h.append(f"    static constexpr double colour_err_f16 = {col_err!r};")
+        h.append("};")
+        h.append("")
+        # B fragments of v_mfma_f32_16x16x32_f16 for N (exact in float16): for K step ks
+        # and column tile t, lane l holds N[32 ks + 8 (l/16) + v][16 t + l%16], v = 0..7,
+        # packed two halves per 32-bit word (zero outside N)
+        ks_n, nt_n = (nc + 31) // 32, (nc + 15) // 16
+        if np.abs(Nm).max() > 2048 and np.any((np.abs(Nm) > 2048) & (Nm % 2 != 0)):
+            raise ValueError("colour numerators not exact in float16")
+        words = []
+        for ks in range(ks_n):
+            for t in range(nt_n):
+                for l in range(64):
+                    halves = []
+                    for v in range(8):
+                        k, col = 32 * ks + 8 * (l // 16) + v, 16 * t + l % 16
+                        val = self.num[k][col] if (k < nc and col < nc) else 0
+                        halves.append(int(np.array(val, dtype=np.float16).view(np.uint16)))
+                    words += [halves[2 * i] | (halves[2 * i + 1] << 16) for i in range(4)]
+        h.append(f"// colour-matrix B fragments, [K step {ks_n}][column tile {nt_n}][lane 64][4 words]")
+        h.append(f"__device__ static const unsigned int coop_bfrag_{self.name}[{len(words)}] = {{")
+        for i in range(0, len(words), 16):
+            h.append("    " + ", ".join(f"0x{w:08x}u" for w in words[i:i + 16]) + ",")
         h.append("};")
         h.append("")
         h.append(f"// flow maps of the waves, [wave][local flow]")
@@ -444,6 +484,7 @@ class GGCoopEmitter(GGEmitter):
         h.append("};")
         h.append(f"template <> struct coop_table<proc_{self.name}> {{")
         h.append(f"    static MEV const int* fmap(int w) {{ return coop_fmap_{self.name} + w * {nc}; }}")
+        h.append(f"    static MEV const unsigned int* bfrag() {{ return coop_bfrag_{self.name}; }}")
         h.append("};")
         return "\n".join(h) + "\n"
 

@@ -33,7 +33,9 @@ def me_mod(torch_cuda):
     return me
 
 
-@pytest.mark.parametrize("proc,n,seed", [("gg_tt", 65536, 1), ("gg_ttg", 8192, 7), ("gg_ttgg", 8192, 2)])
+# g g -> t tbar g g g: the oracle takes about a second per event here
+@pytest.mark.parametrize("proc,n,seed", [("gg_tt", 65536, 1), ("gg_ttg", 8192, 7), ("gg_ttgg", 8192, 2),
+                                         ("gg_ttggg", 160, 3)])
 def test_mixed_within_tolerance(me_mod, torch_cuda, proc, n, seed):
     torch = torch_cuda
     mom = process_points(proc, n, seed)
@@ -73,6 +75,36 @@ def test_forced_fallback_is_float64(me_mod, torch_cuda):
     torch.cuda.synchronize()
     assert m.fallback_count() == 1000
     assert torch.equal(got, ref)
+    m.close()
+
+
+def test_forced_fallback_workgroup_kernel(me_mod, torch_cuda):
+    """The same for the workgroup kernel of g g -> t tbar g g g: the rerun goes
+    through the float64 kernel's index form.  Its LDS sums are atomic, so the
+    two float64 evaluations agree to rounding, not bit for bit."""
+    torch = torch_cuda
+    mom = process_points("gg_ttggg", 100, 9)
+    m = me_mod.MatrixElement("gg_ttggg")
+    t = torch.from_numpy(mom).cuda()
+    ref = m.eval(t).clone()
+    m.set_precision(me_mod.ME_MIXED, 1e-14)
+    got = m.eval(t)
+    torch.cuda.synchronize()
+    assert m.fallback_count() == 100
+    torch.testing.assert_close(got, ref, rtol=1e-13, atol=0)
+    m.close()
+
+
+def test_mixed_ragged_workgroup_kernel(me_mod, torch_cuda):
+    """Partial tiles of the workgroup kernel's mixed form, and repeated calls."""
+    torch = torch_cuda
+    m = me_mod.MatrixElement("gg_ttggg")
+    m.set_precision(me_mod.ME_MIXED, TOL)
+    for n, seed in ((65, 3), (1, 4)):
+        mom = process_points("gg_ttggg", n, seed)
+        got = m.eval(torch.from_numpy(mom).cuda()).cpu().numpy()
+        want = oracle.me2("gg_ttggg", mom)
+        assert np.abs(got / want - 1).max() <= TOL
     m.close()
 
 
