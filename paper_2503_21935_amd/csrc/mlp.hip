@@ -121,6 +121,90 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
 }
 
 // ---------------------------------------------------------------------------
+// Fused inference for width 256: a block of 256 threads (4 waves) carries a
+// tile of 128 rows through every layer with the activations in LDS, so the
+// only HBM traffic is the input, the output and (from L2) the weights.  Per
+// layer, wave w computes output columns 64w..64w+63 for all 128 rows (8 x 4
+// MFMA tiles of 16 x 16, K steps of 32); after a barrier the bias + SiLU
+// epilogue writes the BF16 activations over the layer's input.  Numerics as
+// in the layered path: BF16 inputs, weights and activations, FP32
+// accumulation, FP32 bias, activation and output layer.
+// ---------------------------------------------------------------------------
+#define MLPF_ROWS 128
+#define MLPF_W 256
+#define MLPF_PITCH (MLPF_W + 8)  // bf16 per LDS row: rows 528 B apart, no bank conflicts
+#define MLPF_MAXDEPTH 8
+
+struct mlpf_args {
+    const bf16* w[MLPF_MAXDEPTH];   // hidden layers, [256][K] (K = 32 for the first, padded)
+    const float* b[MLPF_MAXDEPTH];  // their biases [256]
+    const float* wout;              // output weights [256]
+    const float* bout;              // output bias [1]
+};
+
+__global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ x, int64_t n, int n_in, int depth,
+                                                      mlpf_args a, float* __restrict__ y) {
+    __shared__ __attribute__((aligned(16))) bf16 H[MLPF_ROWS * MLPF_PITCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * MLPF_ROWS;
+    for (int e = threadIdx.x; e < MLPF_ROWS * MLP_KPAD; e += 256) {
+        const int r = e / MLP_KPAD, k = e % MLP_KPAD;
+        const int64_t gr = row0 + r;
+        H[r * MLPF_PITCH + k] = (bf16)((gr < n && k < n_in) ? x[gr * n_in + k] : 0.f);
+    }
+    __syncthreads();
+    const int li = lane & 15, lg = lane >> 4;
+    int K = MLP_KPAD;
+    for (int l = 0; l < depth; ++l) {
+        f32x4 acc[8][4];
+#pragma unroll
+        for (int rt = 0; rt < 8; ++rt)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[rt][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const bf16* W = a.w[l];
+        for (int k0 = 0; k0 < K; k0 += 32) {
+            bf16x8 b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                b[t] = *reinterpret_cast<const bf16x8*>(W + (int64_t)(64 * wave + 16 * t + li) * K + k0 + 8 * lg);
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(H + (16 * rt + li) * MLPF_PITCH + k0 + 8 * lg);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[rt][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[t], acc[rt][t], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave has read the layer's input
+        const float* bias = a.b[l];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int c = 64 * wave + 16 * t + li;
+            const float bc = bias[c];
+#pragma unroll
+            for (int rt = 0; rt < 8; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float z = acc[rt][t][v] + bc;
+                    H[(16 * rt + 4 * lg + v) * MLPF_PITCH + c] = (bf16)(z * sigmoidf_(z));
+                }
+        }
+        __syncthreads();
+        K = MLPF_W;
+    }
+    // output layer, as k_last_fwd: y = sum_k h[k] w[k] + b, sequential in k
+    if (threadIdx.x < MLPF_ROWS) {
+        const int r = threadIdx.x;
+        const int64_t gr = row0 + r;
+        if (gr < n) {
+            float s = 0.f;
+            for (int k = 0; k < MLPF_W; ++k) s = fmaf((float)H[r * MLPF_PITCH + k], a.wout[k], s);
+            y[gr] = s + a.bout[0];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Element-wise and reduction kernels
 // ---------------------------------------------------------------------------
 
@@ -518,6 +602,19 @@ int mlp_forward(me_mlp* p, const float* x, int64_t n, float* y, void* stream) {
     if (n == 0) return ME_OK;
     if (!x || !y) return me_fail(ME_EINVAL, "mlp_forward: null buffer");
     hipStream_t s = (hipStream_t)stream;
+    if (p->width == MLPF_W && p->n_in <= MLP_KPAD && p->depth <= MLPF_MAXDEPTH) {
+        mlpf_args a{};
+        for (int l = 0; l < p->depth; ++l) {
+            a.w[l] = p->wbf[l];
+            a.b[l] = p->theta + p->L.b_off[l];
+        }
+        a.wout = p->theta + p->wout_off;
+        a.bout = p->theta + p->bout_off;
+        hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((n + MLPF_ROWS - 1) / MLPF_ROWS)), dim3(256), 0, s, x, n,
+                           p->n_in, p->depth, a, y);
+        HCHK(hipGetLastError());
+        return ME_OK;
+    }
     const int64_t chunk = 1 << 16;
     int rc = ensure_acts(p, std::min<int64_t>(n, chunk));
     if (rc != ME_OK) return rc;
