@@ -81,6 +81,10 @@ int me_init(const char *process, const double *couplings, int n_couplings, const
  * stream:  hipStream_t (NULL = default stream); no host synchronisation.
  * nevt == 0 launches nothing.  Errors: ME_EINVAL (null pointer, nevt < 0),
  * ME_EDEVICE (launch failure).
+ * Reproducibility: results are deterministic for every process except
+ * "gg_ttggg", whose kernel adds the contributions of four waves into shared
+ * colour-flow amplitudes with atomic float64 adds; its results agree from run
+ * to run to rounding (relative 1e-15 level), not bit for bit.
  */
 int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, void *stream);
 

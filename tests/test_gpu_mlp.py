@@ -199,3 +199,86 @@ def test_unweighting_matches_reference(me_mod, torch_cuda):
     print(f"[unweight] {n} points: stage 1 kept {n1}, accepted {n2}", flush=True)
     ctx.close()
     net.close()
+
+
+def test_surrogate_gain_and_unbiasedness(me_mod, torch_cuda):
+    """What the trained network gains: on g g -> t tbar g g points (generator
+    cuts as in the benchmark) the two-stage unweighting needs several times
+    fewer exact matrix elements per effective unweighted event than
+    unweighting with the exact matrix element alone, and its estimate of the
+    mean weight stays unbiased (within 5 standard deviations computed from each
+    point's exact acceptance probability and output weight)."""
+    import math
+
+    from inputs import gluon_cuts
+
+    torch = torch_cuda
+    dev = torch.device("cuda")
+    ctx = me_mod.MatrixElement("gg_ttgg")
+    # training set labelled by the float64 GPU kernel
+    mom_tr = process_points("gg_ttgg", 1 << 17, 4, precise=False)
+    mom_tr = mom_tr[gluon_cuts(mom_tr)]
+    mt = torch.from_numpy(mom_tr).to(dev)
+    lab = torch.log(ctx.eval(mt))
+    mu, sig = float(lab.mean()), float(lab.std())
+    t = ((lab - mu) / sig).float()
+    x = me_mod.features(mt)
+    net = me_mod.Surrogate(seed=21)
+    rng = np.random.default_rng(8)
+    n = (len(t) // 4096) * 4096
+    steps = 0
+    total = 6 * (n // 4096)
+    for _ in range(6):
+        perm = torch.from_numpy(rng.permutation(n).astype(np.int32)).to(dev)
+        for b in range(n // 4096):
+            lr = 0.5e-3 * (1 + math.cos(math.pi * steps / total))
+            net.train_step(x, t, perm[b * 4096:(b + 1) * 4096], lr)
+            steps += 1
+    # maxima from an independent calibration sample
+    mom_c, w_c = process_points("gg_ttgg", 1 << 17, 6, return_weight=True, precise=False)
+    w_c = w_c * gluon_cuts(mom_c)
+    mc = torch.from_numpy(mom_c).to(dev)
+    s_c = (torch.exp(sig * net.forward(me_mod.features(mc)).double() + mu) * torch.from_numpy(w_c).to(dev)).cpu().numpy()
+    we_c = (ctx.eval(mc) * torch.from_numpy(w_c).to(dev)).cpu().numpy()
+    pos = s_c > 0
+    s_max = float(np.quantile(s_c[pos], 0.999))
+    r_max = float(np.quantile(we_c[pos] / s_c[pos], 0.999))
+    w_max = float(np.quantile(we_c[pos], 0.999))
+    # unweighting sample
+    nu = 1 << 18
+    mom_u, w_u = process_points("gg_ttgg", nu, 5, return_weight=True, precise=False)
+    w_u = w_u * gluon_cuts(mom_u)
+    u = uniforms(nu, 2, 55)
+    tm, tw, tu = (torch.from_numpy(a).to(dev) for a in (mom_u, w_u, u))
+    out_idx = torch.empty(nu, dtype=torch.int32, device=dev)
+    out_w = torch.empty(nu, dtype=torch.float64, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int32, device=dev)
+    me_mod.unweight_two_stage(ctx.ctx, net.h, tm, tw, nu, tu, mu, sig, s_max, r_max, out_idx, out_w, cnt)
+    torch.cuda.synchronize()
+    n1, n2 = cnt.cpu().numpy().tolist()
+    wt2 = out_w[:n2].cpu().numpy()
+    neff2 = wt2.sum() ** 2 / (wt2 ** 2).sum()
+    s = (torch.exp(sig * net.forward(me_mod.features(tm)).double() + mu) * tw).cpu().numpy()
+    w = (ctx.eval(tm) * tw).cpu().numpy()
+    # exact-only unweighting of the same points: every point with w_ps > 0 needs the exact ME
+    n_exact_only = int((w_u > 0).sum())
+    acc1 = u[:, 0] < np.minimum(1.0, w / w_max)
+    wt1 = np.maximum(1.0, w / w_max)[acc1]
+    neff1 = wt1.sum() ** 2 / (wt1 ** 2).sum()
+    gain = (n_exact_only / neff1) / (n1 / neff2)
+    print(f"[gain] exact calls per effective event: exact-only {n_exact_only / neff1:.0f}, "
+          f"two-stage {n1 / neff2:.0f} (stage 1 kept {n1} of {nu}, accepted {n2}); gain {gain:.1f}", flush=True)
+    assert gain > 2.0
+    # unbiasedness: E[s_max r_max * sum of output weights] = sum of w
+    ok = s > 0
+    ratio = np.where(ok, w / np.where(ok, s, 1.0), 0.0)
+    p_acc = np.where(ok, np.minimum(1, s / s_max) * np.minimum(1, ratio / r_max), 0.0)
+    out_wt = np.maximum(1, s / s_max) * np.maximum(1, ratio / r_max)
+    c2 = (s_max * r_max * out_wt) ** 2 * p_acc
+    var = np.sum(c2 - w ** 2)
+    est = s_max * r_max * wt2.sum()
+    print(f"[gain] mean-weight estimate {est / nu:.4e} vs exact {w.sum() / nu:.4e} "
+          f"({(est - w.sum()) / math.sqrt(var):+.2f} sigma)", flush=True)
+    assert abs(est - w.sum()) < 5 * math.sqrt(var)
+    ctx.close()
+    net.close()
