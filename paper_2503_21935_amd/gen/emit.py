@@ -202,7 +202,9 @@ class GGEmitter:
                 cands = [v for v in live if v not in protect]
                 if not cands:
                     break
-                victim = max(cands, key=lambda v: next_use(v, t))
+                # ties broken by the node itself, so that the emitted program does
+                # not depend on set iteration order (string hashing per process)
+                victim = max(cands, key=lambda v: (next_use(v, t), repr(v)))
                 live.discard(victim)
             ops.append(node)
             live.add(node)

@@ -170,3 +170,23 @@ def test_register_window_replays_to_direct_sums(coop5):
             J[k] += v
         np.testing.assert_allclose(J, direct, atol=1e-12)
     e.window = 16
+
+
+def test_generated_programs_do_not_depend_on_hash_seed():
+    """The emitted HIP source is a function of the process alone (no set
+    iteration order leaks into the schedule), so builds are reproducible."""
+    import subprocess
+    import sys
+
+    code = ("import sys, hashlib; sys.path.insert(0, %r)\n"
+            "from paper_2503_21935_amd.gen.emit import GGEmitter\n"
+            "from paper_2503_21935_amd.gen.coop import GGCoopEmitter\n"
+            "a = GGEmitter('gg_ttgg', 4, True, cap=14, cap_f32=20).render()\n"
+            "b = GGCoopEmitter('gg_ttggg', 5, True, cap=16, window=16).render()\n"
+            "print(hashlib.sha256((a + b).encode()).hexdigest())\n") % ROOT
+    digests = set()
+    for seed in ("1", "2"):
+        env = dict(os.environ, PYTHONHASHSEED=seed)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, check=True)
+        digests.add(r.stdout.strip())
+    assert len(digests) == 1
