@@ -16,6 +16,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 #define MLP_KPAD 32  // first-layer inputs padded to one MFMA K step
+#define MLP_DW_SPLITS 16  // batch splits of the weight-gradient GEMMs
 
 // ---------------------------------------------------------------------------
 // GEMM: C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m * a_sm + k * a_sk],
@@ -37,6 +38,7 @@ struct epi_args {
     bf16* dz;           // BWD_DH: output gradient w.r.t. those pre-activations [M][N]
     float* g;           // DW: gradient [M][N] row-major with leading dimension ldg
     int ldg;
+    int64_t zstride;    // DW with split K: elements between the partial slabs of blockIdx.z
     int ncols_store;    // DW: columns actually stored (n_in for the first layer)
 };
 
@@ -74,10 +76,12 @@ __device__ __forceinline__ void load_frags(const bf16* __restrict__ A, int64_t a
     }
 }
 
+// Split K: block z of gridDim.z handles k in [z kspan, (z + 1) kspan) (kspan a
+// multiple of 32); only the DW epilogue supports it (one partial slab per z).
 template <int EPI, bool AK1, bool BK1>
-__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* __restrict__ A, int64_t a_sm,
-                                              int64_t a_sk, const bf16* __restrict__ B, int64_t b_sk,
-                                              int64_t b_sn, epi_args e) {
+__global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, int kspan, const bf16* __restrict__ A,
+                                              int64_t a_sm, int64_t a_sk, const bf16* __restrict__ B,
+                                              int64_t b_sk, int64_t b_sn, epi_args e) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.y * 64 + (wave >> 1) * 32;
     const int col0 = blockIdx.x * 64 + (wave & 1) * 32;
@@ -86,7 +90,8 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    const int kb = blockIdx.z * kspan, ke = min(K, kb + kspan);
+    for (int k0 = kb; k0 < ke; k0 += 32) {
         bf16x8 a[2], b[2];
         load_frags<AK1, BK1>(A, a_sm, a_sk, B, b_sk, b_sn, row0, col0, k0, M, N, lane, a, b);
 #pragma unroll
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const bf16* _
                     const float s = sigmoidf_(z);
                     e.dz[(int64_t)r * N + c] = (bf16)(x * s * (1.f + z * (1.f - s)));
                 } else {
-                    if (c < e.ncols_store) e.g[(int64_t)r * e.ldg + c] = x;
+                    if (c < e.ncols_store) e.g[(int64_t)blockIdx.z * e.zstride + (int64_t)r * e.ldg + c] = x;
                 }
             }
         }
@@ -277,19 +282,23 @@ __global__ void k_last_bwd(const float* __restrict__ dy, const float* __restrict
     dZ[i] = (bf16)(dy[m] * w[n] * s * (1.f + z * (1.f - s)));
 }
 
-// out[n] = sum_m coef(m) A[m][n], coef = dy[m] or 1; one block per 64 columns.
+// part[z][n] = sum over rows m of chunk z of coef(m) A[m][n] (coef = dy[m] or 1);
+// block (x, z) covers 64 columns of row chunk z; k_sum_splits adds the chunks.
 template <typename TA>
-__global__ void k_colsum(const TA* __restrict__ A, const float* __restrict__ coef, int64_t M, int N,
-                         float* __restrict__ out) {
+__global__ void k_colsum_part(const TA* __restrict__ A, const float* __restrict__ coef, int64_t M, int N,
+                              int64_t rows, float* __restrict__ part) {
     __shared__ float red[4][64];
     const int c = blockIdx.x * 64 + (threadIdx.x & 63);
     const int rg = threadIdx.x >> 6;
+    const int64_t m0 = (int64_t)blockIdx.y * rows, m1 = (m0 + rows < M) ? m0 + rows : M;
     float s = 0.f;
     if (c < N)
-        for (int64_t m = rg; m < M; m += 4) s = fmaf(coef ? coef[m] : 1.f, (float)A[m * N + c], s);
+        for (int64_t m = m0 + rg; m < m1; m += 4) s = fmaf(coef ? coef[m] : 1.f, (float)A[m * N + c], s);
     red[rg][threadIdx.x & 63] = s;
     __syncthreads();
-    if (rg == 0 && c < N) out[c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    if (rg == 0 && c < N)
+        part[(int64_t)blockIdx.y * N + c] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
 // out[0] = sum_m dy[m]
@@ -363,6 +372,7 @@ struct me_mlp {
     layer_map L;
     int64_t wout_off, bout_off;
     float *theta, *grad, *m, *v;
+    float* dwpart;           // split-K partial slabs of one weight gradient [MLP_DW_SPLITS][width][fan_in]
     std::vector<bf16*> wbf;  // per hidden layer, [width][ld]
     bf16** d_wbf;            // device array of those pointers
     int64_t cap;             // activation capacity (rows)
@@ -438,10 +448,35 @@ static hipError_t refresh_bf16(me_mlp* p, hipStream_t s) {
 }
 
 template <int EPI, bool AK1, bool BK1>
-static void gemm(hipStream_t s, int M, int N, int K, const bf16* A, int64_t a_sm, int64_t a_sk, const bf16* B,
-                 int64_t b_sk, int64_t b_sn, const epi_args& e) {
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-    hipLaunchKernelGGL((k_gemm<EPI, AK1, BK1>), grid, dim3(256), 0, s, M, N, K, A, a_sm, a_sk, B, b_sk, b_sn, e);
+// Returns the number of K splits launched (partial slabs for EPI_DW).
+static int gemm(hipStream_t s, int M, int N, int K, const bf16* A, int64_t a_sm, int64_t a_sk, const bf16* B,
+                int64_t b_sk, int64_t b_sn, const epi_args& e, int splits = 1) {
+    const int kspan = ((K + splits - 1) / splits + 31) / 32 * 32;
+    splits = (K + kspan - 1) / kspan;
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64), (unsigned)splits);
+    hipLaunchKernelGGL((k_gemm<EPI, AK1, BK1>), grid, dim3(256), 0, s, M, N, K, kspan, A, a_sm, a_sk, B, b_sk, b_sn,
+                       e);
+    return splits;
+}
+
+// out[i] = sum over z < splits of part[z n + i] (fixed order: deterministic)
+__global__ void k_sum_splits(const float* __restrict__ part, int splits, int64_t n, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float acc = 0.f;
+    for (int z = 0; z < splits; ++z) acc += part[(int64_t)z * n + i];
+    out[i] = acc;
+}
+
+// out[n] = sum_m coef(m) A[m][n] over all M rows, in row chunks (partials in
+// p->dwpart, summed in a fixed order).
+static void colsum(hipStream_t s, const bf16* A, const float* coef, int64_t M, int N, float* scratch, float* out) {
+    const int64_t chunks = std::min<int64_t>(64, (M + 63) / 64);
+    const int64_t rows = (M + chunks - 1) / chunks;
+    hipLaunchKernelGGL((k_colsum_part<bf16>), dim3((unsigned)((N + 63) / 64), (unsigned)chunks), dim3(256), 0, s, A,
+                       coef, M, N, rows, scratch);
+    hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, scratch, (int)chunks,
+                       (int64_t)N, out);
 }
 
 // Forward over rows [0, M) of p->X; training keeps Z and every H.
@@ -477,8 +512,7 @@ static void backward(me_mlp* p, const float* t, const int32_t* idx, int64_t M, f
     if (loss) hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, p->partial, (int)nb, M, loss);
     bf16* Hl = p->H[p->depth - 1];
     // output layer: dw_out = sum_m dy[m] H[m][:], db_out = sum dy
-    hipLaunchKernelGGL((k_colsum<bf16>), dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, Hl, p->dy, M, W,
-                       p->grad + p->wout_off);
+    colsum(s, Hl, p->dy, M, W, p->dwpart, p->grad + p->wout_off);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, p->dy, M, p->grad + p->bout_off);
     hipLaunchKernelGGL(k_last_bwd, dim3((unsigned)((M * W + 255) / 256)), dim3(256), 0, s, p->dy,
                        p->theta + p->wout_off, p->Z[p->depth - 1], M, W, p->dZa);
@@ -488,13 +522,20 @@ static void backward(me_mlp* p, const float* t, const int32_t* idx, int64_t M, f
         const bf16* hin = (l == 0) ? p->X : p->H[l - 1];
         const int fi = p->L.fan_in[l], ldin = (l == 0) ? MLP_KPAD : W;
         // dW_l[n][k] = sum_m dZ[m][n] hin[m][k]: A(n, m) = dZ[m][n], B(m, k) = hin[m][k]
+        // split over the batch (K): 16 x 16 blocks instead of 16, partial slabs summed after
+        const int splits = (int)std::min<int64_t>(MLP_DW_SPLITS, std::max<int64_t>(1, M / 256));
         epi_args e{};
-        e.g = p->grad + p->L.w_off[l];
+        e.g = splits > 1 ? p->dwpart : p->grad + p->L.w_off[l];
         e.ldg = fi;
         e.ncols_store = fi;
-        gemm<EPI_DW, false, false>(s, W, ldin, (int)M, dz, 1, W, hin, ldin, 1, e);
-        hipLaunchKernelGGL((k_colsum<bf16>), dim3((unsigned)((W + 63) / 64)), dim3(256), 0, s, dz, nullptr, M, W,
-                           p->grad + p->L.b_off[l]);
+        e.zstride = (int64_t)W * fi;
+        const int used = gemm<EPI_DW, false, false>(s, W, ldin, (int)M, dz, 1, W, hin, ldin, 1, e, splits);
+        if (splits > 1) {
+            const int64_t nw = (int64_t)W * fi;
+            hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, p->dwpart, used, nw,
+                               p->grad + p->L.w_off[l]);
+        }
+        colsum(s, dz, nullptr, M, W, p->dwpart, p->grad + p->L.b_off[l]);
         if (l > 0) {
             // dH_{l-1}[m][k] = sum_n dZ[m][n] W_l[n][k]; fused silu'(Z_{l-1})
             epi_args e2{};
@@ -556,7 +597,8 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
         return false;
     };
     if (bad(hipMalloc(&p->theta, o * sizeof(float))) || bad(hipMalloc(&p->grad, o * sizeof(float))) ||
-        bad(hipMalloc(&p->m, o * sizeof(float))) || bad(hipMalloc(&p->v, o * sizeof(float))))
+        bad(hipMalloc(&p->m, o * sizeof(float))) || bad(hipMalloc(&p->v, o * sizeof(float))) ||
+        bad(hipMalloc(&p->dwpart, (size_t)MLP_DW_SPLITS * width * width * sizeof(float))))
         return me_fail(ME_ENOMEM, "mlp_create: device allocation");
     for (int l = 0; l < depth; ++l) {
         const int ld = (l == 0) ? MLP_KPAD : p->L.fan_in[l];
@@ -672,6 +714,7 @@ int mlp_free(me_mlp* p) {
     };
     f(p->theta);
     f(p->grad);
+    f(p->dwpart);
     f(p->m);
     f(p->v);
     for (auto q : p->wbf) f(q);
