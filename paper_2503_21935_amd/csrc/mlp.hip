@@ -197,15 +197,22 @@ __global__ __launch_bounds__(256, 2) void k_mlp_infer(const float* __restrict__ 
         __syncthreads();
         K = MLPF_W;
     }
-    // output layer, as k_last_fwd: y = sum_k h[k] w[k] + b, sequential in k
-    if (threadIdx.x < MLPF_ROWS) {
-        const int r = threadIdx.x;
-        const int64_t gr = row0 + r;
-        if (gr < n) {
-            float s = 0.f;
-            for (int k = 0; k < MLPF_W; ++k) s = fmaf((float)H[r * MLPF_PITCH + k], a.wout[k], s);
-            y[gr] = s + a.bout[0];
+    // output layer: y = sum_k h[k] w[k] + b; two threads per row (adjacent lanes),
+    // each over half of the columns in 16-byte reads, then one exchange
+    {
+        const int r = threadIdx.x >> 1, half = threadIdx.x & 1;
+        const bf16x8* hr = reinterpret_cast<const bf16x8*>(H + r * MLPF_PITCH + half * (MLPF_W / 2));
+        const float* wo = a.wout + half * (MLPF_W / 2);
+        float s = 0.f;
+#pragma unroll 4
+        for (int k8 = 0; k8 < MLPF_W / 16; ++k8) {
+            const bf16x8 v = hr[k8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s = fmaf((float)v[q], wo[8 * k8 + q], s);
         }
+        s += __shfl_xor(s, 1);
+        const int64_t gr = row0 + r;
+        if (half == 0 && gr < n) y[gr] = s + a.bout[0];
     }
 }
 
