@@ -18,8 +18,9 @@ GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # g g -> t tbar g g runs fastest at 14 (49.5 ms per 2^20 events against
 # 50.5 ms at 12, which has no private memory at all, and 44 bytes of it per
 # lane at 14); g g -> t tbar g g g (workgroup program, J in LDS, window of 16)
-# runs 334 ms per 2^18 events at 16 (132 bytes of private memory per lane)
-# against 418 ms at 8 and 364 ms at 12; 18 and 20 spill more and gain nothing.
+# ran 334 ms per 2^18 events at 16 against 418 ms at 8 and 364 ms at 12 (18
+# and 20 spill more and gain nothing); with the cache-aware amplitude order
+# of the workgroup program it runs 304 ms at 16.
 LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14, "gg_ttggg": 16}
 LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 # Processes whose colour-flow amplitudes are kept in LDS by a workgroup of
