@@ -190,3 +190,25 @@ def test_generated_programs_do_not_depend_on_hash_seed():
         r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, check=True)
         digests.add(r.stdout.strip())
     assert len(digests) == 1
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch):
+    """No silent fallback: with libme.so absent the binding raises."""
+    import paper_2503_21935_amd as me
+
+    monkeypatch.setattr(me, "_lib", None)
+    monkeypatch.setattr(me, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libme.so"))
+    with pytest.raises(ImportError, match="no fallback"):
+        me.lib()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """This build runs on one GPU: --gpus 2 exits with a message (before any GPU work)."""
+    import json
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
