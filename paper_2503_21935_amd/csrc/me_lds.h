@@ -6,7 +6,9 @@
 #pragma once
 #include "me_process.h"
 
-// J_k += v (atomic: several waves add into the same J_k)
+// J_k += v (atomic: several waves add into the same J_k).  On MI355X the
+// float64 form (ds_add_f64) is fast; the float32 one (ds_add_f32) was
+// measured about 20 times slower per wave instruction.
 template <typename T>
 MEV void lds_acc(T* __restrict__ Jl, int k, const cx<T>& v) {
     atomicAdd(Jl + (2 * k) * 64, v.r);
@@ -34,6 +36,9 @@ MEV int fmap_at(int t0, int t1) {
         return __builtin_amdgcn_readlane(t1, K - 64);
 }
 
+// New values of a and b as far as the compiler can tell (no instruction is
+// emitted): lane reads of them after this point cannot be merged with reads
+// before it.
 MEV void opaque_int(int& a, int& b) { asm volatile("" : "+v"(a), "+v"(b)); }
 
 // External wavefunctions and constants of the workgroup program.  The
@@ -66,6 +71,7 @@ MEV mom4<double> pick_mom(int a, const mom4<double>& x, const mom4<double>& y) {
 }
 
 // Per-process tables of the workgroup kernel: fmap(w)[k] is the flow of J
-// that local flow k of the shared program becomes in wave w.
+// that local flow k of the shared program becomes in wave w; bfrag() the
+// packed float16 B fragments of the colour numerators for the mixed form.
 template <class P>
 struct coop_table;
