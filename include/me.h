@@ -117,7 +117,8 @@ int me_eval_mixed_diag(me_ctx *ctx, const double *momenta, int64_t nevt, double 
 
 /*
  * me_fallback_count -- number of events the last mixed me_eval recomputed in
- * float64.  Synchronises the device.  0 before any mixed evaluation.
+ * float64.  Synchronises the device (all streams) before it reads the count.
+ * 0 before any mixed evaluation.
  */
 int me_fallback_count(me_ctx *ctx, int64_t *count);
 

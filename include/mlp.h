@@ -43,6 +43,10 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp **out);
 /* mlp_n_params -- number of FP32 parameters. */
 int mlp_n_params(const me_mlp *mlp, int64_t *n);
 
+/* mlp_dims -- the network's input count, hidden width and depth (any output
+ * pointer may be NULL). */
+int mlp_dims(const me_mlp *mlp, int *n_in, int *width, int *depth);
+
 /* mlp_get_params / mlp_set_params -- copy the FP32 master parameters to / from
  * a host array of n = mlp_n_params entries (flat layout above).  Both
  * synchronise the device; set also refreshes the BF16 working copy. */

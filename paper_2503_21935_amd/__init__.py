@@ -95,6 +95,25 @@ def _dev_ptr(t, dtype_name, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t, n, what):
+    """Refuse a buffer with fewer than n elements (a kernel would write or read
+    past its end)."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{what} holds {t.numel()} elements, the call touches {n}")
+
+
+def _nevt(nevt):
+    # a negative count is passed on: the library refuses it with ME_EINVAL
+    return int(nevt)
+
+
+def _ctx_sizes(ctx):
+    """(npart, nhel) of a context, from me_info."""
+    npart, nhel = ctypes.c_int(), ctypes.c_int()
+    _check(lib().me_info(ctx, ctypes.byref(npart), None, None, ctypes.byref(nhel), None, None), "me_info")
+    return npart.value, nhel.value
+
+
 # --------------------------------------------------------------------------
 # C-named wrappers
 # --------------------------------------------------------------------------
@@ -108,11 +127,20 @@ def me_init(process: str, couplings=DEFAULT_COUPLINGS, masses=DEFAULT_MASSES) ->
 
 
 def me_eval(ctx, momenta, nevt: int, out_me2, stream=None) -> None:
+    nevt = _nevt(nevt)
+    npart, _ = _ctx_sizes(ctx)
+    _need(momenta, nevt * npart * 4, "momenta")
+    _need(out_me2, nevt, "out_me2")
     _check(lib().me_eval(ctx, _dev_ptr(momenta, "float64", "momenta"), int(nevt),
                          _dev_ptr(out_me2, "float64", "out_me2"), _stream_handle(stream)), "me_eval")
 
 
 def me_eval_helicities(ctx, momenta, nevt: int, out_me2, out_qhel, stream=None) -> None:
+    nevt = _nevt(nevt)
+    npart, nhel = _ctx_sizes(ctx)
+    _need(momenta, nevt * npart * 4, "momenta")
+    _need(out_me2, nevt, "out_me2")
+    _need(out_qhel, nevt * nhel, "out_qhel")
     _check(lib().me_eval_helicities(ctx, _dev_ptr(momenta, "float64", "momenta"), int(nevt),
                                     _dev_ptr(out_me2, "float64", "out_me2"),
                                     _dev_ptr(out_qhel, "float64", "out_qhel"), _stream_handle(stream)),
@@ -142,6 +170,11 @@ def me_set_precision(ctx, mode: int, rel_tol: float = 1e-5) -> None:
 
 
 def me_eval_mixed_diag(ctx, momenta, nevt: int, out_me2, out_err, out_flag, stream=None) -> None:
+    nevt = _nevt(nevt)
+    npart, _ = _ctx_sizes(ctx)
+    _need(momenta, nevt * npart * 4, "momenta")
+    for t, what in ((out_me2, "out_me2"), (out_err, "out_err"), (out_flag, "out_flag")):
+        _need(t, nevt, what)
     _check(lib().me_eval_mixed_diag(ctx, _dev_ptr(momenta, "float64", "momenta"), int(nevt),
                                     _dev_ptr(out_me2, "float64", "out_me2"), _dev_ptr(out_err, "float32", "out_err"),
                                     _dev_ptr(out_flag, "uint8", "out_flag"), _stream_handle(stream)),
@@ -251,6 +284,8 @@ def _mlp_sigs(L):
         return L
     L.mlp_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(vp)]
     L.mlp_n_params.argtypes = [vp, ctypes.POINTER(i64)]
+    L.mlp_dims.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                           ctypes.POINTER(ctypes.c_int)]
     L.mlp_get_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
     L.mlp_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
     L.mlp_forward.argtypes = [vp, vp, i64, vp, vp]
@@ -280,6 +315,24 @@ def mlp_n_params(h) -> int:
     return n.value
 
 
+def mlp_dims(h):
+    """(n_in, width, depth) of a network."""
+    v = [ctypes.c_int() for _ in range(3)]
+    _check(_mlp_sigs(lib()).mlp_dims(h, *[ctypes.byref(x) for x in v]), "mlp_dims")
+    return tuple(x.value for x in v)
+
+
+def _batch_checks(h, x, t, idx, n):
+    n = int(n)
+    if idx is not None:
+        _need(idx, n, "idx")
+    else:
+        n_in = mlp_dims(h)[0]
+        _need(x, n * n_in, "x")
+        _need(t, n, "t")
+    return n
+
+
 def mlp_get_params(h):
     import numpy as np
 
@@ -298,11 +351,16 @@ def mlp_set_params(h, params) -> None:
 
 
 def mlp_forward(h, x, n, y, stream=None) -> None:
+    n = _nevt(n)
+    _need(x, n * mlp_dims(h)[0], "x")
+    _need(y, n, "y")
     _check(_mlp_sigs(lib()).mlp_forward(h, _dev_ptr(x, "float32", "x"), int(n), _dev_ptr(y, "float32", "y"),
                                         _stream_handle(stream)), "mlp_forward")
 
 
 def mlp_train_step(h, x, t, idx, n, lr, loss=None, stream=None) -> None:
+    n = _batch_checks(h, x, t, idx, n)
+    _need(loss, 1, "loss")
     _check(_mlp_sigs(lib()).mlp_train_step(h, _dev_ptr(x, "float32", "x"), _dev_ptr(t, "float32", "t"),
                                            _opt_ptr(idx, "int32", "idx"), int(n), float(lr),
                                            _opt_ptr(loss, "float32", "loss"), _stream_handle(stream)),
@@ -310,6 +368,9 @@ def mlp_train_step(h, x, t, idx, n, lr, loss=None, stream=None) -> None:
 
 
 def mlp_backward(h, x, t, idx, n, grad, loss=None, stream=None) -> None:
+    n = _batch_checks(h, x, t, idx, n)
+    _need(grad, mlp_n_params(h), "grad")
+    _need(loss, 1, "loss")
     _check(_mlp_sigs(lib()).mlp_backward(h, _dev_ptr(x, "float32", "x"), _dev_ptr(t, "float32", "t"),
                                          _opt_ptr(idx, "int32", "idx"), int(n), _dev_ptr(grad, "float32", "grad"),
                                          _opt_ptr(loss, "float32", "loss"), _stream_handle(stream)), "mlp_backward")
@@ -320,12 +381,23 @@ def mlp_free(h) -> None:
 
 
 def me_features(momenta, n, npart, x, stream=None) -> None:
+    n = _nevt(n)
+    _need(momenta, n * int(npart) * 4, "momenta")
+    _need(x, n * int(npart) * 4, "x")
     _check(_mlp_sigs(lib()).me_features(_dev_ptr(momenta, "float64", "momenta"), int(n), int(npart),
                                         _dev_ptr(x, "float32", "x"), _stream_handle(stream)), "me_features")
 
 
 def unweight_two_stage(ctx, mlp, momenta, w_ps, n, uniforms, y_mu, y_sigma, s_max, r_max, out_idx, out_w,
                        out_count, stream=None) -> None:
+    n = _nevt(n)
+    npart, _ = _ctx_sizes(ctx)
+    _need(momenta, n * npart * 4, "momenta")
+    _need(w_ps, n, "w_ps")
+    _need(uniforms, 2 * n, "uniforms")
+    _need(out_idx, n, "out_idx")
+    _need(out_w, n, "out_w")
+    _need(out_count, 2, "out_count")
     _check(_mlp_sigs(lib()).unweight_two_stage(
         ctx, mlp, _dev_ptr(momenta, "float64", "momenta"), _dev_ptr(w_ps, "float64", "w_ps"), int(n),
         _dev_ptr(uniforms, "float64", "uniforms"), float(y_mu), float(y_sigma), float(s_max), float(r_max),

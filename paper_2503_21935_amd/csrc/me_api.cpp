@@ -256,6 +256,9 @@ int me_fallback_count(me_ctx* c, int64_t* count) {
     *count = 0;
     if (!c->d_count) return ME_OK;
     int v = 0;
+    // the mixed evaluation may have run on a non-blocking stream, which a copy
+    // on the null stream does not wait for
+    HIP_CHECK(hipDeviceSynchronize());
     HIP_CHECK(hipMemcpy(&v, c->d_count, sizeof(int), hipMemcpyDeviceToHost));
     *count = v;
     return ME_OK;

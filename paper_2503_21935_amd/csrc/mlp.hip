@@ -639,6 +639,14 @@ int mlp_n_params(const me_mlp* p, int64_t* n) {
     return ME_OK;
 }
 
+int mlp_dims(const me_mlp* p, int* n_in, int* width, int* depth) {
+    if (!p) return me_fail(ME_EINVAL, "null network");
+    if (n_in) *n_in = p->n_in;
+    if (width) *width = p->width;
+    if (depth) *depth = p->depth;
+    return ME_OK;
+}
+
 int mlp_get_params(me_mlp* p, float* host, int64_t n) {
     if (!p || !host || n != p->np) return me_fail(ME_EINVAL, "mlp_get_params: null or wrong size");
     HCHK(hipDeviceSynchronize());

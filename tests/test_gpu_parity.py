@@ -208,6 +208,62 @@ def test_empty_and_errors(me_mod, torch_cuda):
     assert e.value.status == me_mod.ME_EINVAL
 
 
+def test_binding_refuses_short_buffers(me_mod, torch_cuda):
+    """Buffers shorter than the call touches are refused before the C call."""
+    torch = torch_cuda
+    m = get_me(me_mod, "gg_tt")
+    mom = torch.from_numpy(process_points("gg_tt", 64, 1)).cuda()
+    short = torch.empty(63, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        me_mod.me_eval(m.ctx, mom, 64, short)
+    with pytest.raises(ValueError):
+        me_mod.me_eval(m.ctx, mom[:32], 64, torch.empty(64, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.me_eval_helicities(m.ctx, mom, 64, torch.empty(64, dtype=torch.float64, device="cuda"),
+                                  torch.empty(64 * 16 - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.me_eval_mixed_diag(m.ctx, mom, 64, torch.empty(64, dtype=torch.float64, device="cuda"),
+                                  torch.empty(64, dtype=torch.float32, device="cuda"),
+                                  torch.empty(10, dtype=torch.uint8, device="cuda"))
+    net = me_mod.Surrogate(n_in=16, width=64, depth=1, seed=3)
+    x = torch.zeros(100, 16, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        me_mod.mlp_forward(net.h, x, 101, torch.empty(101, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.mlp_forward(net.h, x, 100, torch.empty(99, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.mlp_backward(net.h, x, torch.zeros(64, dtype=torch.float32, device="cuda"), None, 128,
+                            torch.empty(net.n_params, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.me_features(mom, 64, 4, torch.empty(64 * 16 - 1, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        me_mod.unweight_two_stage(m.ctx, net.h, mom, torch.ones(64, dtype=torch.float64, device="cuda"), 64,
+                                  torch.full((64, 2), 0.5, dtype=torch.float64, device="cuda"), 0.0, 1.0, 1.0,
+                                  1.0, torch.empty(64, dtype=torch.int32, device="cuda"),
+                                  torch.empty(64, dtype=torch.float64, device="cuda"),
+                                  torch.empty(1, dtype=torch.int32, device="cuda"))
+    net.close()
+
+
+def test_fallback_count_after_a_side_stream(me_mod, torch_cuda):
+    """The fallback count of a mixed evaluation on a non-blocking stream is read
+    after that stream's work (me_fallback_count waits for the whole device)."""
+    torch = torch_cuda
+    m = me_mod.MatrixElement("gg_ttgg")
+    mom = torch.from_numpy(process_points("gg_ttgg", 1 << 15, 2)).cuda()
+    m.set_precision(me_mod.ME_MIXED, 1e-5)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        out = m.eval(mom, stream=side)
+        n_side = m.fallback_count()  # no host synchronisation before this call
+    torch.cuda.synchronize()
+    _, _, flag = m.eval_mixed_diag(mom)
+    torch.cuda.synchronize()
+    assert n_side == int(flag.sum().item()) > 0
+    m.close()
+
+
 def test_two_contexts_two_streams(me_mod, torch_cuda):
     torch = torch_cuda
     a = me_mod.MatrixElement("gg_ttg")
