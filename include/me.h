@@ -122,6 +122,29 @@ int me_eval_mixed_diag(me_ctx *ctx, const double *momenta, int64_t nevt, double 
  */
 int me_fallback_count(me_ctx *ctx, int64_t *count);
 
+/* Largest nevt me_eval_mixed_noalloc accepts. */
+#define ME_NOALLOC_MAX_NEVT (1 << 20)
+
+/*
+ * me_eval_mixed_noalloc -- me_eval in the mixed form (tolerance as set by
+ * me_set_precision, default 1e-5; the context's mode is not consulted) with no
+ * device allocation: for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * momenta, out_me2, stream: as in me_eval.  The flagged-event counter and
+ * index list of the float64 rerun live in a fixed library-owned scratch array
+ * on each device (4 MiB + 256 B, allocated at load time, held until the
+ * process ends), whose address is looked up when a context is created on
+ * that device.  Every call on one GPU shares that array and the last call's
+ * contents remain; the counter is cleared by a kernel at the start of each
+ * call, so two calls that overlap on one GPU (different streams, or threads)
+ * race and must be ordered by the caller.  Processes without a mixed form
+ * (e+e- -> mu+mu-) are evaluated in float64 and touch no scratch.
+ * me_fallback_count does not report the events of this call.
+ * Errors: ME_EINVAL (null pointer, nevt < 0, nevt > ME_NOALLOC_MAX_NEVT),
+ * ME_ESTATE (current device is not the context's), ME_EDEVICE.
+ */
+int me_eval_mixed_noalloc(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, void *stream);
+
 /*
  * me_eval_helicities -- per-helicity contributions, for checks.
  * out_qhel: device pointer, float64 [nevt][nhel]; entry h receives

@@ -52,6 +52,7 @@ def lib():
     L.me_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_double]
     L.me_eval_mixed_diag.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.me_fallback_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.me_eval_mixed_noalloc.argtypes = [vp, vp, i64, vp, vp]
     L.me_free.argtypes = [vp]
     L.me_strerror.argtypes = [ctypes.c_int]
     L.me_strerror.restype = ctypes.c_char_p
@@ -179,6 +180,16 @@ def me_eval_mixed_diag(ctx, momenta, nevt: int, out_me2, out_err, out_flag, stre
                                     _dev_ptr(out_me2, "float64", "out_me2"), _dev_ptr(out_err, "float32", "out_err"),
                                     _dev_ptr(out_flag, "uint8", "out_flag"), _stream_handle(stream)),
            "me_eval_mixed_diag")
+
+
+def me_eval_mixed_noalloc(ctx, momenta, nevt: int, out_me2, stream=None) -> None:
+    nevt = _nevt(nevt)
+    npart, _ = _ctx_sizes(ctx)
+    _need(momenta, nevt * npart * 4, "momenta")
+    _need(out_me2, nevt, "out_me2")
+    _check(lib().me_eval_mixed_noalloc(ctx, _dev_ptr(momenta, "float64", "momenta"), int(nevt),
+                                       _dev_ptr(out_me2, "float64", "out_me2"), _stream_handle(stream)),
+           "me_eval_mixed_noalloc")
 
 
 def me_fallback_count(ctx) -> int:

@@ -43,6 +43,35 @@ static int ensure_scratch(me_ctx* c, int64_t nevt) {
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free mixed evaluation (me_eval_mixed_noalloc):
+// a flagged-event counter in the first 256 bytes, then the flagged-event
+// index list for up to ME_NOALLOC_MAX_NEVT events (4 MiB + 256 B per device,
+// held until the process ends).  Host code never uses the array's name as an
+// address: the device address is looked up once per device, with that device
+// current, and kept in g_scratch_ptr.
+// ---------------------------------------------------------------------------
+#define ME_SCRATCH_HEAD 64  // ints before the index list (256 bytes)
+static __device__ __align__(256) int scratch[ME_SCRATCH_HEAD + ME_NOALLOC_MAX_NEVT];
+
+static std::mutex g_scratch_mu;
+static int* g_scratch_ptr[ME_MAX_DEVICES];
+static std::string g_scratch_err[ME_MAX_DEVICES];
+
+// Looks up the current device's copy of `scratch` (once per device).
+static void resolve_scratch(int device) {
+    if (device < 0 || device >= ME_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    int* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        g_scratch_err[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return;
+    }
+    g_scratch_ptr[device] = ptr;
+}
+
+// ---------------------------------------------------------------------------
 // Probe points for the helicity filter: flat massless n-body momenta from a
 // fixed splitmix64 stream, rescaled to the final-state masses (the RAMBO
 // construction of Kleiss, Stirling and Ellis).  Generic points: a helicity
@@ -191,6 +220,7 @@ int me_init(const char* process, const double* couplings, int n_couplings, const
         delete c;
         return fail(ME_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
+    resolve_scratch(c->device);
     std::vector<int> all(pd->nhel);
     for (int h = 0; h < pd->nhel; ++h) all[h] = h;
     if (hipMalloc(&c->d_all, pd->nhel * sizeof(int)) != hipSuccess ||
@@ -226,6 +256,31 @@ int me_eval(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, voi
         return ME_OK;
     }
     HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, s));
+    return ME_OK;
+}
+
+int me_eval_mixed_noalloc(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, void* stream) {
+    if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
+    if (nevt == 0) return ME_OK;
+    if (!momenta || !out_me2) return fail(ME_EINVAL, "null buffer");
+    if (nevt > ME_NOALLOC_MAX_NEVT)
+        return fail(ME_EINVAL, "nevt above ME_NOALLOC_MAX_NEVT (" + std::to_string(ME_NOALLOC_MAX_NEVT) + ")");
+    int dev = -1;
+    HIP_CHECK(hipGetDevice(&dev));
+    if (dev != c->device) return fail(ME_ESTATE, "the current device is not the context's device");
+    hipStream_t s = (hipStream_t)stream;
+    if (!c->proc->launch_mixed) {  // no mixed form (e+e- -> mu+mu-): float64, no scratch
+        HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, s));
+        return ME_OK;
+    }
+    int* base = g_scratch_ptr[dev];
+    if (!base) return fail(ME_EDEVICE, g_scratch_err[dev].empty() ? "scratch not resolved" : g_scratch_err[dev]);
+    int* d_count = base;
+    int* d_idx = base + ME_SCRATCH_HEAD;
+    // the mixed launch clears the counter with a kernel before it appends
+    HIP_CHECK(c->proc->launch_mixed(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, (float)c->tol,
+                                    (float)c->proc->mixed_cest, d_count, d_idx, nullptr, nullptr, s));
+    HIP_CHECK(c->proc->launch_f64_idx(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, d_idx, d_count, s));
     return ME_OK;
 }
 

@@ -9,6 +9,9 @@
 #include "../../include/me.h"
 #include "me_launch.h"
 
+// Devices the allocation-free entry point keeps a scratch address for.
+#define ME_MAX_DEVICES 64
+
 // Records the detail string for me_last_error() and returns code.
 int me_fail(int code, const std::string& msg);
 
