@@ -70,6 +70,38 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(v, 0.001 * g * g)
 
 
+def test_adam_constant_gradient_every_step():
+    """With the same gradient g at every step, the bias-corrected moments are
+    exactly g and g^2 at every t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so
+    each update is lr g / (|g| + eps).  A bias correction with the wrong power
+    of b1 or b2 breaks this from t = 2 on."""
+    rng = np.random.default_rng(11)
+    th0 = rng.normal(size=40)
+    g = rng.normal(size=40) * np.logspace(-4, 2, 40)
+    th, m, v = th0.copy(), np.zeros(40), np.zeros(40)
+    lr = 3e-3
+    for t in range(1, 6):
+        new, m, v = R.adam_step(th, m, v, g, t, lr)
+        np.testing.assert_allclose(new - th, -lr * g / (np.abs(g) + 1e-8), rtol=1e-10, atol=0, err_msg=f"t={t}")
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=1e-12)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12)
+        th = new
+
+
+def test_adam_sign_flip_second_step():
+    """Gradient g then -g: m_2 = 0.9*0.1 g - 0.1 g = -0.01 g, bias-corrected by
+    1 - 0.81 = 0.19; v_2 = 0.999*0.001 g^2 + 0.001 g^2 = 0.001999 g^2, corrected
+    by 1 - 0.998001 = 0.001999, i.e. exactly g^2.  The second update is
+    therefore -lr (-0.01/0.19) g / (|g| + eps) = +lr g / (19 (|g| + eps))."""
+    rng = np.random.default_rng(12)
+    th0 = rng.normal(size=30)
+    g = rng.normal(size=30)
+    lr = 1e-2
+    th1, m, v = R.adam_step(th0, np.zeros(30), np.zeros(30), g, 1, lr)
+    th2, m, v = R.adam_step(th1, m, v, -g, 2, lr)
+    np.testing.assert_allclose(th2 - th1, lr * g / (19 * (np.abs(g) + 1e-8)), rtol=1e-9)
+
+
 def test_training_lowers_the_loss():
     th, dims = small_net(4)
     rng = np.random.default_rng(5)
