@@ -33,12 +33,24 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "me_oracle.c")
 _LIBS = {False: os.path.join(_HERE, "liboracle.so"), True: os.path.join(_HERE, "liboracle_quad.so")}
+_PS_SRC = os.path.join(_HERE, "ps_oracle.c")
+_PS_LIB = os.path.join(_HERE, "liboracle_ps.so")
 
 PROCESS_NGLUON = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 
 
+def _build_ps(force: bool = True) -> None:
+    if not force and os.path.exists(_PS_LIB) and os.path.getmtime(_PS_LIB) >= os.path.getmtime(_PS_SRC):
+        return
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-Wall", "-o", _PS_LIB + ".tmp", _PS_SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_PS_LIB + ".tmp", _PS_LIB)
+
+
 def build(force: bool = True) -> None:
-    """Compile the double and __float128 variants with gcc."""
+    """Compile the double and __float128 variants of the matrix-element oracle
+    and the phase-space oracle with gcc."""
+    _build_ps(force)
     for quad, lib in _LIBS.items():
         if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
             continue
@@ -191,3 +203,53 @@ def me2_dressed(n: int, mom1, params=None, per_helicity: bool = False):
     if rc != 0:
         raise RuntimeError("oracle failed")
     return (out[0], qh) if per_helicity else out[0]
+
+
+# --------------------------------------------------------------------------
+# Phase-space sampling (ps_oracle.c): Philox4x32-10 and RAMBO
+# --------------------------------------------------------------------------
+
+@functools.lru_cache(maxsize=None)
+def _ps_lib():
+    _build_ps(force=False)
+    lib = ctypes.CDLL(_PS_LIB)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_philox4x32.argtypes = [u32p, u32p, ctypes.c_int, u32p]
+    lib.oracle_event_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, dp]
+    lib.oracle_rambo.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64,
+                                 ctypes.c_int64, dp, dp, dp]
+    return lib
+
+
+def philox4x32(ctr, key, rounds: int = 10):
+    """Philox4x32 block function (Salmon et al., SC'11): four 32-bit words."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    _ps_lib().oracle_philox4x32(c, k, int(rounds), o)
+    return [int(v) for v in o]
+
+
+def event_uniforms(seed: int, event: int, n: int) -> np.ndarray:
+    """The n uniforms of one event of the phase-space stream."""
+    out = np.empty(n)
+    _ps_lib().oracle_event_uniforms(int(seed), int(event), int(n), _ptr(out))
+    return out
+
+
+def rambo(roots: float, masses, seed: int, first: int, n_evt: int, cond: bool = False):
+    """Flat phase-space points (momenta [n][nf + 2][4], weights [n]) of events
+    first .. first + n_evt - 1 of the Philox stream `seed` (RAMBO map); with
+    cond=True also the per-event factor (Q0/M)^2 by which the map enlarges
+    rounding in the generated directions and energies."""
+    m = np.ascontiguousarray(masses, dtype=np.float64)
+    nf = m.size
+    mom = np.empty((n_evt, nf + 2, 4))
+    wt = np.empty(n_evt)
+    cd = np.empty(n_evt) if cond else None
+    rc = _ps_lib().oracle_rambo(float(roots), _ptr(m), nf, int(seed), int(first), int(n_evt), _ptr(mom), _ptr(wt),
+                                _ptr(cd))
+    if rc != 0:
+        raise ValueError("oracle_rambo: bad arguments")
+    return (mom, wt, cd) if cond else (mom, wt)
