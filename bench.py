@@ -109,12 +109,137 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8, tol=None):
         m.set_precision(me.ME_FP64, tol)
     m.close()
     achieved = info["flops_per_event"] * nevt / k_s / 1e12
-    kernel = f"k_me_gg_coop<proc_{proc}>" if proc == "gg_ttggg" else f"k_me_gg<proc_{proc}>"
+    kernel = {"gg_ttggg": f"k_me_gg_coop<proc_{proc}>", "ee_mumu": "k_me_ee<proc_ee_mumu>"}.get(
+        proc, f"k_me_gg<proc_{proc}>")
     return {"workload": f"{proc}, {nevt} RAMBO points seed {seed}", "MEs_per_s": nevt / wall, "kernel": kernel,
             "traffic": traffic_from_profile(proc, kernel),
             "kernel_ms": k_s * 1e3, "flops_per_event": info["flops_per_event"],
             "achieved_tflops": achieved, "frac_of_fp64_peak": achieved / PEAK["fp64"],
             "max_rel_dev_vs_oracle": float(rel.max()), "checked_events": check, "mixed": mixed}
+
+
+def nevt_sweep(me, proc, seed, lanes_list, logs, stream):
+    """MEs/s of the float64 kernel against the number of events per launch, for
+    one lane per event and for helicity-parallel launches (2^k lanes per event)."""
+    import torch
+
+    from inputs import process_points
+
+    nmax = 1 << max(logs)
+    mom_all = torch.from_numpy(process_points(proc, nmax, seed, precise=False)).cuda()
+    m = me.MatrixElement(proc)
+    rows = []
+    for lanes in lanes_list:
+        m.set_helicity_lanes(lanes)
+        for lg in logs:
+            n = 1 << lg
+            mom = mom_all[:n]
+            out = torch.empty(n, dtype=torch.float64, device=mom.device)
+            reps = max(3, min(200, (1 << 22) // n))
+            m.eval(mom, out=out, stream=stream)
+            k_s, _ = timed(lambda: m.eval(mom, out=out, stream=stream), reps, stream)
+            rows.append({"lanes_per_event": lanes, "nevt": n, "kernel_ms": k_s * 1e3, "MEs_per_s": n / k_s})
+        log(f"sweep {proc} lanes {lanes}: " + ", ".join(f"2^{lg} {r['MEs_per_s']:.2e}"
+                                                       for lg, r in zip(logs, rows[-len(logs):])))
+    m.close()
+    return {"process": proc, "timing": "HIP events on the launch stream, average per launch", "points": rows}
+
+
+def bench_phase_space(me, stream, n, host_s):
+    """GPU phase-space sampling (Philox4x32-10 + RAMBO) of the benchmark's
+    workload: 2^20 g g -> t tbar g g points; bound by the HBM write of the
+    momenta and weights (192 + 8 bytes per point)."""
+    import torch
+
+    masses = [173.0, 173.0, 0.0, 0.0]
+    mom = torch.empty((n, 6, 4), dtype=torch.float64, device="cuda")
+    wt = torch.empty(n, dtype=torch.float64, device="cuda")
+    me.ps_rambo(13000.0, masses, 2, 0, n, mom, wt, stream)
+    k_s, _ = timed(lambda: me.ps_rambo(13000.0, masses, 2, 0, n, mom, wt, stream), 20, stream)
+    nbytes = n * (6 * 4 * 8 + 8)
+    return {"workload": f"{n} g g -> t tbar g g points, sqrt(s) = 13 TeV", "kernel": "k_ps_rambo<4>",
+            "points_per_s": n / k_s, "kernel_ms": k_s * 1e3,
+            "roofline": {"bound": "hbm", "achieved": nbytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": 200},
+            "host_numpy_rambo_s_same_size": host_s}
+
+
+def bench_colour_forms(me, stream, cases):
+    """Float64 kernel time with the colour sum on the VALU (symmetric form) and
+    as a float64 MFMA GEMM over block pairs (me_set_colour_form)."""
+    import torch
+
+    from inputs import process_points
+
+    out = {}
+    for proc, n, seed, steps in cases:
+        mom = torch.from_numpy(process_points(proc, n, seed, precise=False)).cuda()
+        res = torch.empty(n, dtype=torch.float64, device="cuda")
+        m = me.MatrixElement(proc)
+        row = {"nevt": n}
+        vals = {}
+        for name, form in (("valu", me.ME_COLOUR_VALU), ("mfma", me.ME_COLOUR_MFMA)):
+            m.set_colour_form(form)
+            m.eval(mom, out=res, stream=stream)
+            k_s, _ = timed(lambda: m.eval(mom, out=res, stream=stream), steps, stream)
+            vals[name] = res.clone()
+            row[f"{name}_kernel_ms"] = k_s * 1e3
+            row[f"{name}_MEs_per_s"] = n / k_s
+        row["max_rel_diff_between_forms"] = float(((vals["mfma"] / vals["valu"]) - 1).abs().max())
+        m.close()
+        out[proc] = row
+        log(f"colour forms {proc}: {row}")
+    return out
+
+
+def parity_adjudication(proc, mom_np, got, ref, tol=1e-12):
+    """Events beyond tol against the float64 oracle, re-evaluated with the
+    __float128 oracle: their deviation from the quad result and the spread of
+    the quad result under 2^-52 relative perturbations of the input momenta."""
+    import numpy as np
+
+    import oracle
+
+    rel = np.abs(got / ref - 1)
+    bad = np.nonzero(rel > tol)[0]
+    out = {"events": int(len(got)), "beyond_1e-12_vs_double_oracle": int(bad.size),
+           "max_rel_dev_vs_double_oracle": float(rel.max())}
+    if bad.size:
+        q0 = oracle.me2(proc, mom_np[bad], quad=True)
+        rng = np.random.default_rng(1)
+        spread = np.zeros(bad.size)
+        for _ in range(4):
+            pert = mom_np[bad] * (1 + rng.choice([-1.0, 1.0], size=mom_np[bad].shape) * 2.0 ** -52)
+            spread = np.maximum(spread, np.abs(oracle.me2(proc, pert, quad=True) / q0 - 1))
+        rq = np.abs(got[bad] / q0 - 1)
+        ok = (rq <= tol) | (rq <= 10 * spread)
+        out.update({"their_max_rel_dev_vs_quad_oracle": float(rq.max()),
+                    "their_max_input_rounding_spread": float(spread.max()),
+                    "within_1e-12_of_quad_or_10x_spread": int(ok.sum())})
+    return out
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def omp_threads(n=None):
+    """Set (n given) or read the OpenMP thread count of the oracle's runtime."""
+    import ctypes
+
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
 
 
 def bench_mixed(me, m, mom, mom_np, args, stream):
@@ -140,8 +265,18 @@ def bench_mixed(me, m, mom, mom_np, args, stream):
     rel_raw = np.abs(raw[idx] / ref - 1)
     m.set_precision(me.ME_FP64, args.tol)
     n = mom.shape[0]
+    info = m.info()
+    # composite bound: amplitudes at the float32 vector peak, colour form (dense
+    # quadratic form, 4 ncol^2 + 4 ncol per event and helicity) at the FP16 MFMA peak
+    f_col = info["nhel_good"] * (4 * info["ncol"] ** 2 + 4 * info["ncol"])
+    f_amp = info["flops_per_event"] - info["nhel_good"] * info["flops_colour_per_hel"]
+    t_min = n * (f_amp / (PEAK["fp32"] * 1e12) + f_col / (PEAK["bf16_mfma"] * 1e12))
     return {
         "MEs_per_s": n / wall, "ms_per_step": wall * 1e3, "tolerance": args.tol,
+        "roofline": {"bound": "composite: fp32 vector (amplitudes) + fp16 mfma (colour)",
+                     "t_min_ms": t_min * 1e3, "mixed_kernel_ms": diag_s * 1e3, "frac": t_min / diag_s,
+                     "frac_incl_rerun": t_min / k_s,
+                     "flops_amplitudes_per_event": f_amp, "flops_colour_per_event": f_col},
         "fallback_fraction": nfb / n,
         "mixed_kernel_ms_without_rerun": diag_s * 1e3,
         "max_rel_err_vs_oracle": float(rel.max()),
@@ -253,8 +388,11 @@ def bench_surrogate(me, args, stream):
     gain = (one_s / max(neff1, 1e-30)) / (two_s / max(neff2, 1e-30))
     ctx.close()
     net.close()
+    train_rate = total * args.batch / train_s
     return {
-        "train_samples_per_s": total * args.batch / train_s, "train_epochs": args.epochs,
+        "train_samples_per_s": train_rate, "train_epochs": args.epochs,
+        "train_tflops": 3 * mlp_flops * train_rate / 1e12,
+        "train_frac_of_bf16_mfma_peak": 3 * mlp_flops * train_rate / 1e12 / PEAK["bf16_mfma"],
         "train_points": int(n_fit), "val_mse_standardised_log_me2": val_mse,
         "inference_samples_per_s": n / inf_s,
         "inference_tflops": mlp_flops * n / inf_s / 1e12,
@@ -279,8 +417,13 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
     ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg",
-                    help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3)")
+    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,configs,sweep,ps,colour",
+                    help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3); "
+                         "configs: e+e- -> mu+mu- (16384 points, seed 0) and g g -> t tbar (2^20, seed 1); "
+                         "sweep: events per launch 2^10..2^20 at 1, 4, 16, 64 lanes per event; "
+                         "ps: the GPU phase-space sampler on the benchmark's workload; "
+                         "colour: float64 kernels with the colour sum on the VALU and on the matrix cores")
+    ap.add_argument("--cpu-sample-1t", type=int, default=4096, help="events for the single-thread oracle figure")
     ap.add_argument("--n-train", type=int, default=1 << 22)
     ap.add_argument("--n-calib", type=int, default=1 << 20)
     ap.add_argument("--n-unweight", type=int, default=1 << 22)
@@ -318,7 +461,8 @@ def main():
         del a, b
     t0 = time.time()
     mom_np = process_points(args.process, args.nevt, args.seed)
-    log(f"generated {args.nevt} points in {time.time() - t0:.1f}s")
+    host_gen_s = time.time() - t0
+    log(f"generated {args.nevt} points on the host in {host_gen_s:.1f}s")
     mom = torch.from_numpy(mom_np).to(dev)
     out = torch.empty(args.nevt, dtype=torch.float64, device=dev)
     m = me.MatrixElement(args.process)
@@ -365,24 +509,46 @@ def main():
         line["forms"]["surrogate"] = bench_surrogate(me, args, stream)
         log(f"surrogate: {line['forms']['surrogate']}")
 
+    line["processes"] = {}
     if "gg_ttggg" in forms:
-        line["processes"] = {"gg_ttggg": bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream,
-                                                       tol=args.tol if "mixed" in forms else None)}
+        line["processes"]["gg_ttggg"] = bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream,
+                                                      tol=args.tol if "mixed" in forms else None)
         log(f"gg_ttggg: {line['processes']['gg_ttggg']}")
+    if "configs" in forms:
+        line["processes"]["ee_mumu"] = bench_process(me, "ee_mumu", 16384, 0, args.steps, stream, check=64)
+        line["processes"]["gg_tt"] = bench_process(me, "gg_tt", 1 << 20, 1, args.steps, stream, check=64)
+        log(f"configs: ee_mumu {line['processes']['ee_mumu']['MEs_per_s']:.3e}, "
+            f"gg_tt {line['processes']['gg_tt']['MEs_per_s']:.3e} MEs/s")
+    if "colour" in forms:
+        line["colour_forms"] = bench_colour_forms(me, stream, [("gg_ttgg", args.nevt, args.seed, 5),
+                                                                ("gg_ttggg", 1 << 18, 3, 2)])
+    if "ps" in forms:
+        line["phase_space"] = bench_phase_space(me, stream, args.nevt, host_gen_s)
+        log(f"phase space: {line['phase_space']['points_per_s']:.3e} points/s")
+    if "sweep" in forms:
+        line["nevt_sweep"] = nevt_sweep(me, args.process, args.seed, [1, 4, 16, 64], list(range(10, 21, 2)), stream)
 
     if not args.no_cpu:
         import oracle
 
         n = min(args.cpu_sample, args.nevt)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        threads = omp_threads()
         c0 = time.perf_counter()
         ref = oracle.me2(args.process, mom_np[:n])
         cpu_s = time.perf_counter() - c0
-        rel = np.abs(res[:n] / ref - 1)
+        n1 = min(args.cpu_sample_1t, n)
+        omp_threads(1)
+        c0 = time.perf_counter()
+        oracle.me2(args.process, mom_np[:n1])
+        cpu1_s = time.perf_counter() - c0
+        omp_threads(threads)
         line["cpu_baseline"] = {"value": n / cpu_s, "unit": "MEs/s", "cores": threads, "kind": "oracle",
                                 "sample": f"first {n} of the {args.nevt} points, float64 oracle "
-                                          f"(colour-ordered Berends-Giele), {cpu_s:.1f} s"}
-        line["fp64_max_rel_dev_vs_oracle_on_sample"] = float(rel.max())
+                                          f"(colour-ordered Berends-Giele, OpenMP over events), {cpu_s:.1f} s",
+                                "single_thread_MEs_per_s": n1 / cpu1_s,
+                                "single_thread_sample": f"first {n1} points, {cpu1_s:.1f} s",
+                                "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count()}
+        line["fp64_parity_on_cpu_sample"] = parity_adjudication(args.process, mom_np[:n], res[:n], ref)
     print(json.dumps(line), flush=True)
 
 

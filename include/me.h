@@ -47,9 +47,12 @@ enum {
 };
 
 enum { ME_FP64 = 0, ME_MIXED = 1 };
+enum { ME_COLOUR_VALU = 0, ME_COLOUR_MFMA = 1 };
 
 /*
  * me_init -- create a context for one process on the current HIP device.
+ * (Paper Sec. 2: the matrix-element library is initialised once per process
+ * with the model's couplings and masses, then called on batches of events.)
  *
  * process: "ee_mumu"  e+(1) e-(2) -> mu+(3) mu-(4), s-channel photon + Z
  *          "gg_tt"    g(1) g(2) -> t(3) tbar(4)
@@ -74,6 +77,9 @@ int me_init(const char *process, const double *couplings, int n_couplings, const
 
 /*
  * me_eval -- |M|^2 for nevt points.
+ * (Paper Sec. 2: the data-parallel, reentrant, stateless multi-event call of
+ * the matrix-element step; Sec. 3: its cost is the Feynman-diagram code plus
+ * the colour-matrix quadratic form.)
  * momenta: device pointer, float64 [nevt][npart][4].
  * out_me2: device pointer, float64 [nevt]; receives |M|^2 summed over final
  *          and averaged over initial helicities and colours, divided by the
@@ -90,6 +96,9 @@ int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, v
 
 /*
  * me_set_precision -- choose the evaluation form of later me_eval calls.
+ * (Paper Sec. 3 compares double, float and mixed builds; the mixed form here
+ * is float32 amplitudes with a float16 matrix-core colour sum and a float64
+ * rerun of events whose estimated error exceeds the tolerance.)
  * ME_FP64 (default): float64 throughout.
  * ME_MIXED: float32 wavefunctions and amplitudes (momentum algebra and
  *   propagator denominators in float64), colour sum as a float16 hi/lo GEMM on
@@ -105,7 +114,37 @@ int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, v
 int me_set_precision(me_ctx *ctx, int mode, double rel_tol);
 
 /*
- * me_eval_mixed_diag -- the mixed form without the float64 rerun, for checks.
+ * me_set_helicity_lanes -- helicity-level parallelism of later float64
+ * me_eval calls (the paper's Sec. 2: besides one event per thread, the
+ * helicities of one event can be spread over threads, so that fewer events in
+ * flight fill the GPU).  lanes: 1 (default; one lane sums all helicities of
+ * its event), 2, 4, 8, 16, 32 or 64 lanes per event; each lane sums every
+ * lanes-th filtered helicity and the lanes' partial sums are added when the
+ * event is done.  The result equals the one-lane result up to the order of
+ * the helicity sum.  Applies to the float64 form of me_eval only (the mixed
+ * form, its float64 rerun, me_eval_helicities and unweighting keep one lane
+ * per event).  Errors: ME_EINVAL (null context, lanes not a power of two up
+ * to 64).
+ */
+int me_set_helicity_lanes(me_ctx *ctx, int lanes);
+
+/*
+ * me_set_colour_form -- where later float64 me_eval and me_eval_helicities
+ * calls evaluate the colour sum J^dag C J (the colour-matrix quadratic form of
+ * the paper's Sec. 3).  ME_COLOUR_VALU (default): per event on the vector
+ * ALU, using the symmetry of C.  ME_COLOUR_MFMA: batched over the events of a
+ * tile as a float64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64) over
+ * block pairs of the symmetric C, from J staged in LDS.  Both give the same
+ * result up to rounding; which one is faster depends on the process (the
+ * measured choice is the default).  Errors: ME_EINVAL (unknown form),
+ * ME_ESTATE (the process has no matrix-core colour form: only "gg_ttgg" and
+ * "gg_ttggg" have one).
+ */
+int me_set_colour_form(me_ctx *ctx, int form);
+
+/*
+ * me_eval_mixed_diag -- the mixed form without the float64 rerun, for checks
+ * (the precision study of the paper's Sec. 3, per event).
  * out_me2:  device float64 [nevt], the float32-form result of every event.
  * out_err:  device float32 [nevt], the estimated relative error.
  * out_flag: device uint8 [nevt], 1 where out_err exceeds the context's
@@ -146,7 +185,8 @@ int me_fallback_count(me_ctx *ctx, int64_t *count);
 int me_eval_mixed_noalloc(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, void *stream);
 
 /*
- * me_eval_helicities -- per-helicity contributions, for checks.
+ * me_eval_helicities -- per-helicity contributions, for checks (the helicity
+ * sum of the paper's Sec. 2 taken apart).
  * out_qhel: device pointer, float64 [nevt][nhel]; entry h receives
  *           J_h^dag C J_h (before averaging) for every helicity combination
  *           h in 0..nhel-1 (particle i has helicity + when bit (npart-1-i)
@@ -157,7 +197,8 @@ int me_eval_helicities(me_ctx *ctx, const double *momenta, int64_t nevt, double 
                        void *stream);
 
 /*
- * me_info -- static properties of the context's process.
+ * me_info -- static properties of the context's process (diagrams, colour
+ * flows, helicities: the sizes behind the paper's Sec. 3 cost discussion).
  * Any output pointer may be NULL.  flops_per_event: the algorithmic
  * floating-point operation count of one event over the good helicities
  * (diagram program + colour sum; FMA counted as two operations).
@@ -165,8 +206,23 @@ int me_eval_helicities(me_ctx *ctx, const double *momenta, int64_t nevt, double 
 int me_info(const me_ctx *ctx, int *npart, int *ndiag, int *ncol, int *nhel, int *nhel_good,
             double *flops_per_event);
 
+/*
+ * me_flops -- the floating-point operation counts behind me_info's total, per
+ * helicity (any output may be NULL): amp_per_hel, the diagram part (external
+ * wavefunctions, currents, amplitudes, accumulation into J) with every
+ * wavefunction computed once; colour_per_hel, the colour sum J^dag N J in the
+ * symmetric form the float64 kernels evaluate; executed_per_hel, the diagram
+ * part as the float64 kernel executes it (wavefunctions recomputed under its
+ * register budget included, all waves of a workgroup kernel together).  FMA
+ * counts as two operations.  These are the algorithmic counts of the
+ * roofline accounting (the paper's Sec. 3 splits the cost the same way:
+ * Feynman-diagram code and the colour-matrix quadratic form).
+ */
+int me_flops(const me_ctx *ctx, double *amp_per_hel, double *colour_per_hel, double *executed_per_hel);
+
 /* me_good_helicities -- copy the filtered helicity indices (host array of at
- * least nhel ints); *count receives how many there are. */
+ * least nhel ints); *count receives how many there are.  The filter itself is
+ * not in the paper (see me_init). */
 int me_good_helicities(const me_ctx *ctx, int *out, int *count);
 
 /* me_free -- release the context (NULL is allowed). Synchronises the device. */

@@ -17,6 +17,10 @@
  *
  * Conventions as in me.h: status codes (ME_* from me.h), device pointers owned
  * by the caller, asynchronous on the given stream (NULL = default stream).
+ *
+ * None of this is in the paper (it has no learned component); the two-stage
+ * scheme follows Danziger, Janssen, Schumann, Siegert, SciPost Phys. 12 (2022)
+ * 164, and every call below cites that or the network's own definition.
  */
 #ifndef MLP_H
 #define MLP_H
@@ -32,7 +36,8 @@ extern "C" {
 typedef struct me_mlp me_mlp;
 
 /*
- * mlp_create -- allocate a network on the current device and initialise it:
+ * mlp_create -- allocate a network on the current device and initialise it
+ * (the surrogate of Danziger et al. 2022, here an MLP of the stated shape):
  * weights uniform in +-sqrt(6 / fan_in) (He-uniform), biases 0, from a
  * splitmix64 stream keyed by seed; Adam moments 0, step 0.
  * Constraints: 1 <= n_in <= 32, width a multiple of 64 (<= 1024), depth >= 1.
@@ -54,14 +59,16 @@ int mlp_get_params(me_mlp *mlp, float *host, int64_t n);
 int mlp_set_params(me_mlp *mlp, const float *host, int64_t n);
 
 /*
- * mlp_forward -- y[i] = network(x[i]) for i < n.
+ * mlp_forward -- y[i] = network(x[i]) for i < n (the surrogate's estimate of
+ * the standardised log |M|^2, the first stage of Danziger et al. 2022).
  * x: device float32 [n][n_in]; y: device float32 [n].  BF16 operands, FP32
  * accumulation, FP32 bias and activation.  Works in chunks; any n >= 0.
  */
 int mlp_forward(me_mlp *mlp, const float *x, int64_t n, float *y, void *stream);
 
 /*
- * mlp_train_step -- one Adam step on the mini-batch {x[idx[j]], t[idx[j]]},
+ * mlp_train_step -- one Adam step (Kingma, Ba 2015) on the mini-batch
+ * {x[idx[j]], t[idx[j]]},
  * j < n (idx == NULL: the first n rows).
  * x: device float32 [*][n_in]; t: device float32 targets; idx: device int32 [n].
  * n: batch size, a positive multiple of 64.  lr: learning rate of this step.
@@ -72,7 +79,8 @@ int mlp_train_step(me_mlp *mlp, const float *x, const float *t, const int32_t *i
                    float *loss_dev, void *stream);
 
 /*
- * mlp_backward -- gradient of the batch loss only (no update), for checks.
+ * mlp_backward -- gradient of the batch loss only (no update), for checks
+ * (backpropagation through the network defined above).
  * grad_dev: device float32 [n_params] (flat layout); loss_dev as above.
  */
 int mlp_backward(me_mlp *mlp, const float *x, const float *t, const int32_t *idx, int64_t n, float *grad_dev,

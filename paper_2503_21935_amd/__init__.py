@@ -21,6 +21,7 @@ DEFAULT_MASSES = (91.188, 2.4414, 173.0, 1.4915)    # M_Z, W_Z, M_top, W_top
 
 ME_OK, ME_EINVAL, ME_EPROCESS, ME_EDEVICE, ME_ENOMEM, ME_ESTATE = 0, -1, -2, -3, -4, -5
 ME_FP64, ME_MIXED = 0, 1
+ME_COLOUR_VALU, ME_COLOUR_MFMA = 0, 1
 
 NPART = {"ee_mumu": 4, "gg_tt": 4, "gg_ttg": 5, "gg_ttgg": 6, "gg_ttggg": 7}
 
@@ -49,7 +50,10 @@ def lib():
     L.me_eval_helicities.argtypes = [vp, vp, i64, vp, vp, vp]
     L.me_info.argtypes = [vp, ip, ip, ip, ip, ip, dp]
     L.me_good_helicities.argtypes = [vp, ip, ip]
+    L.me_flops.argtypes = [vp, dp, dp, dp]
     L.me_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_double]
+    L.me_set_helicity_lanes.argtypes = [vp, ctypes.c_int]
+    L.me_set_colour_form.argtypes = [vp, ctypes.c_int]
     L.me_eval_mixed_diag.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     L.me_fallback_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.me_eval_mixed_noalloc.argtypes = [vp, vp, i64, vp, vp]
@@ -94,6 +98,10 @@ def _dev_ptr(t, dtype_name, what):
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt_ptr(t, dtype_name, what):
+    return None if t is None else _dev_ptr(t, dtype_name, what)
 
 
 def _need(t, n, what):
@@ -155,6 +163,11 @@ def me_info(ctx) -> dict:
     keys = ["npart", "ndiag", "ncol", "nhel", "nhel_good"]
     out = {k: x.value for k, x in zip(keys, v)}
     out["flops_per_event"] = f.value
+    a, c, x = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().me_flops(ctx, ctypes.byref(a), ctypes.byref(c), ctypes.byref(x)), "me_flops")
+    out["flops_amp_per_hel"] = a.value
+    out["flops_colour_per_hel"] = c.value
+    out["flops_executed_per_hel"] = x.value
     return out
 
 
@@ -168,6 +181,14 @@ def me_good_helicities(ctx) -> list:
 
 def me_set_precision(ctx, mode: int, rel_tol: float = 1e-5) -> None:
     _check(lib().me_set_precision(ctx, int(mode), float(rel_tol)), "me_set_precision")
+
+
+def me_set_helicity_lanes(ctx, lanes: int) -> None:
+    _check(lib().me_set_helicity_lanes(ctx, int(lanes)), "me_set_helicity_lanes")
+
+
+def me_set_colour_form(ctx, form: int) -> None:
+    _check(lib().me_set_colour_form(ctx, int(form)), "me_set_colour_form")
 
 
 def me_eval_mixed_diag(ctx, momenta, nevt: int, out_me2, out_err, out_flag, stream=None) -> None:
@@ -252,6 +273,12 @@ class MatrixElement:
     def set_precision(self, mode, rel_tol=1e-5):
         me_set_precision(self.ctx, mode, rel_tol)
 
+    def set_helicity_lanes(self, lanes):
+        me_set_helicity_lanes(self.ctx, lanes)
+
+    def set_colour_form(self, form):
+        me_set_colour_form(self.ctx, form)
+
     def eval_mixed_diag(self, momenta, stream=None):
         """Mixed form without the float64 rerun: (me2, error estimate, flag)."""
         import torch
@@ -286,6 +313,37 @@ class MatrixElement:
 
 
 # --------------------------------------------------------------------------
+# Phase-space sampling (include/ps.h)
+# --------------------------------------------------------------------------
+
+def ps_rambo(roots, masses, seed, first_event, nevt, momenta, weights=None, stream=None) -> None:
+    L = lib()
+    if not getattr(L, "_ps_ready", False):
+        L.ps_rambo.argtypes = [ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_uint64,
+                               ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L._ps_ready = True
+    nf = len(masses)
+    nevt = _nevt(nevt)
+    _need(momenta, nevt * (nf + 2) * 4, "momenta")
+    _need(weights, nevt, "weights")
+    m = (ctypes.c_double * max(1, nf))(*masses)
+    _check(L.ps_rambo(float(roots), m, nf, int(seed), int(first_event), nevt,
+                      _dev_ptr(momenta, "float64", "momenta"), _opt_ptr(weights, "float64", "weights"),
+                      _stream_handle(stream)), "ps_rambo")
+
+
+def rambo(roots, masses, seed, n, first_event=0, device="cuda", stream=None):
+    """Flat phase-space points generated on the GPU: (momenta [n][nf + 2][4],
+    weights [n]) as float64 device tensors."""
+    import torch
+
+    mom = torch.empty((n, len(masses) + 2, 4), dtype=torch.float64, device=device)
+    wt = torch.empty(n, dtype=torch.float64, device=device)
+    ps_rambo(roots, masses, seed, first_event, n, mom, wt, stream)
+    return mom, wt
+
+
+# --------------------------------------------------------------------------
 # Surrogate network and two-stage unweighting (include/mlp.h)
 # --------------------------------------------------------------------------
 
@@ -308,10 +366,6 @@ def _mlp_sigs(L):
                                      ctypes.c_double, vp, vp, vp, vp]
     L._mlp_ready = True
     return L
-
-
-def _opt_ptr(t, dtype_name, what):
-    return None if t is None else _dev_ptr(t, dtype_name, what)
 
 
 def mlp_create(n_in=24, width=256, depth=4, seed=1004):

@@ -22,6 +22,11 @@ PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"]
 # processes whose colour-flow amplitudes live in LDS (workgroup kernel of me_coop.h)
 COOP = {"gg_ttggg"}
 
+# one-wave processes that also get the float64 form with the colour sum on the
+# matrix cores (needs a multiple of 4 colour flows); the workgroup processes
+# always get it
+CM = {"gg_ttgg"}
+
 # Calibration of the mixed form's amplitude error estimate (multiplies
 # u32 * 2 lambda_max(|N|) |S| |J| / Q); fixed by comparing float32 results
 # with the oracle (see the mixed-precision tests).
@@ -41,10 +46,10 @@ _TU = """// Generated translation unit: kernels of {name}.
 {include}
 
 static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
-                             const me_params& prm, double* qhel, hipStream_t s) {{
-    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+                             const me_params& prm, double* qhel, int lg, hipStream_t s) {{
+    const dim3 grid((unsigned)(((nevt << lg) + ME_BLOCK - 1) / ME_BLOCK));
     hipLaunchKernelGGL(({kernel}<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
-                       qhel, nullptr, nullptr);
+                       qhel, nullptr, nullptr, lg);
     return hipGetLastError();
 }}
 
@@ -52,15 +57,26 @@ static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, c
                                  const me_params& prm, const int* idx, const int* count, hipStream_t s) {{
     const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
     hipLaunchKernelGGL(({kernel}<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
-                       nullptr, idx, count);
+                       nullptr, idx, count, 0);
     return hipGetLastError();
 }}
-{mixed}
+{mixed}{cm}
 #ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
 extern const me_process_desc me_desc_{name} = {{
     "{name}", {kind}, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
-    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, {mixed_ptr}, {cest}, {colerr}}};
+    {proc}::flops_amp, {proc}::flops_colour, {proc}::flops_executed, launch_f64, launch_f64_idx, {mixed_ptr}, {cest},
+    {colerr}, {cm_ptr}}};
 #endif
+"""
+
+_CM = """
+static hipError_t launch_f64_cm(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                const me_params& prm, double* qhel, int lg, hipStream_t s) {{
+    const dim3 grid((unsigned)(((nevt << lg) + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL((k_me_gg_cm<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm, qhel,
+                       nullptr, nullptr, lg);
+    return hipGetLastError();
+}}
 """
 
 _TU_COOP = """// Generated translation unit: kernels of {name} (workgroup form, J in LDS).
@@ -68,10 +84,10 @@ _TU_COOP = """// Generated translation unit: kernels of {name} (workgroup form, 
 {include}
 
 static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
-                             const me_params& prm, double* qhel, hipStream_t s) {{
-    const dim3 grid((unsigned)((nevt + ME_TILE - 1) / ME_TILE));
+                             const me_params& prm, double* qhel, int lg, hipStream_t s) {{
+    const dim3 grid((unsigned)(((nevt << lg) + ME_TILE - 1) / ME_TILE));
     hipLaunchKernelGGL((k_me_gg_coop<{proc}>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out, hels,
-                       nh, prm, qhel, nullptr, nullptr);
+                       nh, prm, qhel, nullptr, nullptr, lg);
     return hipGetLastError();
 }}
 
@@ -79,20 +95,36 @@ static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, c
                                  const me_params& prm, const int* idx, const int* count, hipStream_t s) {{
     const dim3 grid((unsigned)((nevt + ME_TILE - 1) / ME_TILE));
     hipLaunchKernelGGL((k_me_gg_coop<{proc}>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out, hels,
-                       nh, prm, nullptr, idx, count);
+                       nh, prm, nullptr, idx, count, 0);
     return hipGetLastError();
 }}
 
 #ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
-// the mixed-precision launcher is compiled in a translation unit of its own
+// the mixed-precision launcher and the matrix-core colour form are compiled in
+// translation units of their own
 hipError_t me_launch_mixed_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
                                   const me_params& prm, float tol, float cest, int* flag_count, int* flag_idx,
                                   float* err_out, unsigned char* flag_out, hipStream_t s);
+hipError_t me_launch_f64_cm_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                   const me_params& prm, double* qhel, int lg, hipStream_t s);
 extern const me_process_desc me_desc_{name} = {{
     "{name}", ME_KIND_GG, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
-    {proc}::flops_amp, {proc}::flops_colour, launch_f64, launch_f64_idx, me_launch_mixed_{name}, {cest},
-    {proc}::colour_err_f16}};
+    {proc}::flops_amp, {proc}::flops_colour, {proc}::flops_executed, launch_f64, launch_f64_idx, me_launch_mixed_{name}, {cest},
+    {proc}::colour_err_f16, me_launch_f64_cm_{name}}};
 #endif
+"""
+
+_TU_COOP_CM = """// Generated translation unit: float64 kernel of {name} with the colour sum on the matrix cores.
+#include "me_coop.h"
+{include}
+
+hipError_t me_launch_f64_cm_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                   const me_params& prm, double* qhel, int lg, hipStream_t s) {{
+    const dim3 grid((unsigned)(((nevt << lg) + ME_TILE - 1) / ME_TILE));
+    hipLaunchKernelGGL((k_me_gg_coop<{proc}, true>), grid, dim3(ME_TILE * {proc}::waves), 0, s, mom, nevt, out,
+                       hels, nh, prm, qhel, nullptr, nullptr, lg);
+    return hipGetLastError();
+}}
 """
 
 _TU_COOP_MIXED = """// Generated translation unit: mixed-precision kernel of {name} (workgroup form).
@@ -163,16 +195,23 @@ def generate_sources(processes):
             path_m = os.path.join(GEN, f"tu_{name}_mixed.hip")
             _write(path_m, _TU_COOP_MIXED.format(name=name, include=inc, proc=proc))
             tus.append(path_m)
+            path_c = os.path.join(GEN, f"tu_{name}_cm.hip")
+            _write(path_c, _TU_COOP_CM.format(name=name, include=inc, proc=proc))
+            tus.append(path_c)
             continue
+        cm, cm_ptr = ("", "nullptr")
+        if name in CM:
+            cm, cm_ptr = _CM.format(proc=proc), "launch_f64_cm"
         _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind, mixed=mixed,
-                                mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr))
+                                mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr, cm=cm,
+                                cm_ptr=cm_ptr))
         tus.append(path)
     decls = "\n".join(f"extern const me_process_desc me_desc_{n};" for n in processes)
     ptrs = ", ".join(f"&me_desc_{n}" for n in processes)
     reg = os.path.join(GEN, "registry.cpp")
     _write(reg, _REG.format(decls=decls, ptrs=ptrs))
     return tus + [reg, os.path.join(CSRC, "me_api.cpp"), os.path.join(CSRC, "mlp.hip"),
-                  os.path.join(CSRC, "me_unweight.hip")], info
+                  os.path.join(CSRC, "me_unweight.hip"), os.path.join(CSRC, "ps_rambo.hip")], info
 
 
 def _compile(src):

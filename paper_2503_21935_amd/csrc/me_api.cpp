@@ -153,7 +153,7 @@ static int helicity_filter(me_ctx* c) {
     HIP_CHECK(hipMalloc(&d_out, npts * sizeof(double)));
     HIP_CHECK(hipMalloc(&d_q, (size_t)npts * pd->nhel * sizeof(double)));
     HIP_CHECK(hipMemcpy(d_mom, pts.data(), pts.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_CHECK(pd->launch_f64(d_mom, npts, d_out, c->d_all, pd->nhel, c->prm, d_q, nullptr));
+    HIP_CHECK(pd->launch_f64(d_mom, npts, d_out, c->d_all, pd->nhel, c->prm, d_q, 0, nullptr));
     std::vector<double> q((size_t)npts * pd->nhel);
     HIP_CHECK(hipMemcpy(q.data(), d_q, q.size() * sizeof(double), hipMemcpyDeviceToHost));
     HIP_CHECK(hipFree(d_mom));
@@ -170,6 +170,12 @@ static int helicity_filter(me_ctx* c) {
     if (c->nhel_good)
         HIP_CHECK(hipMemcpy(c->d_good, c->good.data(), c->nhel_good * sizeof(int), hipMemcpyHostToDevice));
     return ME_OK;
+}
+
+// The float64 launcher of the context's colour form.
+static me_launch_fn f64_launcher(const me_ctx* c) {
+    return (c->colour_form == ME_COLOUR_MFMA && c->proc->launch_f64_cm) ? c->proc->launch_f64_cm
+                                                                       : c->proc->launch_f64;
 }
 
 extern "C" {
@@ -205,6 +211,8 @@ int me_init(const char* process, const double* couplings, int n_couplings, const
     c->d_good = nullptr;
     c->d_all = nullptr;
     c->mode = ME_FP64;
+    c->hel_lg = 0;
+    c->colour_form = ME_COLOUR_VALU;
     c->tol = 1e-5;
     c->d_count = nullptr;
     c->d_idx = nullptr;
@@ -255,7 +263,26 @@ int me_eval(me_ctx* c, const double* momenta, int64_t nevt, double* out_me2, voi
                                           c->d_count, s));
         return ME_OK;
     }
-    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, s));
+    HIP_CHECK(f64_launcher(c)(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, c->hel_lg, s));
+    return ME_OK;
+}
+
+int me_set_colour_form(me_ctx* c, int form) {
+    if (!c) return fail(ME_EINVAL, "null context");
+    if (form != ME_COLOUR_VALU && form != ME_COLOUR_MFMA)
+        return fail(ME_EINVAL, "form must be ME_COLOUR_VALU or ME_COLOUR_MFMA");
+    if (form == ME_COLOUR_MFMA && !c->proc->launch_f64_cm)
+        return fail(ME_ESTATE, std::string("no matrix-core colour form for ") + c->proc->name);
+    c->colour_form = form;
+    return ME_OK;
+}
+
+int me_set_helicity_lanes(me_ctx* c, int lanes) {
+    if (!c) return fail(ME_EINVAL, "null context");
+    int lg = 0;
+    while (lg <= 6 && (1 << lg) != lanes) ++lg;
+    if (lg > 6) return fail(ME_EINVAL, "lanes per event must be 1, 2, 4, 8, 16, 32 or 64");
+    c->hel_lg = lg;
     return ME_OK;
 }
 
@@ -270,7 +297,7 @@ int me_eval_mixed_noalloc(me_ctx* c, const double* momenta, int64_t nevt, double
     if (dev != c->device) return fail(ME_ESTATE, "the current device is not the context's device");
     hipStream_t s = (hipStream_t)stream;
     if (!c->proc->launch_mixed) {  // no mixed form (e+e- -> mu+mu-): float64, no scratch
-        HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, s));
+        HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, nullptr, 0, s));
         return ME_OK;
     }
     int* base = g_scratch_ptr[dev];
@@ -324,7 +351,7 @@ int me_eval_helicities(me_ctx* c, const double* momenta, int64_t nevt, double* o
     if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
     if (nevt == 0) return ME_OK;
     if (!momenta || !out_me2 || !out_qhel) return fail(ME_EINVAL, "null buffer");
-    HIP_CHECK(c->proc->launch_f64(momenta, nevt, out_me2, c->d_all, c->proc->nhel, c->prm, out_qhel,
+    HIP_CHECK(f64_launcher(c)(momenta, nevt, out_me2, c->d_all, c->proc->nhel, c->prm, out_qhel, 0,
                                   (hipStream_t)stream));
     return ME_OK;
 }
@@ -338,6 +365,14 @@ int me_info(const me_ctx* c, int* npart, int* ndiag, int* ncol, int* nhel, int* 
     if (nhel) *nhel = pd->nhel;
     if (nhel_good) *nhel_good = c->nhel_good;
     if (flops) *flops = c->nhel_good * (pd->flops_amp + pd->flops_colour);
+    return ME_OK;
+}
+
+int me_flops(const me_ctx* c, double* amp_per_hel, double* colour_per_hel, double* executed_per_hel) {
+    if (!c) return fail(ME_EINVAL, "null context");
+    if (amp_per_hel) *amp_per_hel = c->proc->flops_amp;
+    if (colour_per_hel) *colour_per_hel = c->proc->flops_colour;
+    if (executed_per_hel) *executed_per_hel = c->proc->flops_executed;
     return ME_OK;
 }
 

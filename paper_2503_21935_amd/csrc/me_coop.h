@@ -53,21 +53,28 @@ MEV double coop_colour(int wave, const double* Jl) {
 }
 
 // Arguments as for k_me_gg; launched with blocks of 64 * P::waves threads,
-// one block per 64 events (or per 64 entries of idx).
-template <class P>
+// one block per 64 / 2^lg events (or entries of idx).  With lg > 0 the 2^lg
+// lanes of an event take every 2^lg-th helicity of the list (the same count
+// of passes for every lane, so the barriers stay uniform; a lane past the end
+// of the list repeats its last helicity and discards the result).
+// CM: colour sum on the matrix cores (colour_mfma16: wave w takes the tile's
+// columns 16 w .. 16 w + 15 over all flows) instead of the VALU split by
+// blocks of the symmetric matrix (colour_part).
+template <class P, bool CM = false>
 __global__ __launch_bounds__(ME_TILE * P::waves, 1) void k_me_gg_coop(
     const double* __restrict__ mom, int64_t nevt, double* __restrict__ out, const int* __restrict__ hels, int nh,
-    me_params prm, double* __restrict__ qhel, const int* __restrict__ idx, const int* __restrict__ count) {
+    me_params prm, double* __restrict__ qhel, const int* __restrict__ idx, const int* __restrict__ count, int lg) {
     constexpr int NP = P::npart, NG = P::ngluon;
     __shared__ double Jt[P::ncol * 2 * ME_TILE];
     __shared__ double Qt[(NG + 2) * 4 * ME_TILE];
     __shared__ double part[P::waves * ME_TILE];
     const int lane = threadIdx.x % ME_TILE;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / ME_TILE);
+    const int grp = lane & ((1 << lg) - 1);
     const int64_t n = count ? (int64_t)*count : nevt;
-    const int64_t first = (int64_t)blockIdx.x * ME_TILE;
+    const int64_t first = (int64_t)blockIdx.x * (ME_TILE >> lg);
     if (first >= n) return;  // whole block: no barrier is left waiting
-    int64_t i = first + lane;
+    int64_t i = first + (lane >> lg);
     const bool valid = i < n;
     if (!valid) i = n - 1;  // idle lanes repeat an event so that every wave runs the full program
     const int64_t ev = count ? (int64_t)idx[i] : i;
@@ -104,32 +111,59 @@ __global__ __launch_bounds__(ME_TILE * P::waves, 1) void k_me_gg_coop(
     int wsel = wave;
     asm volatile("" : "+v"(wsel));  // per-lane copy: selects instead of branches in the program
     double acc = 0.0;
+    const int passes = (nh + (1 << lg) - 1) >> lg;
 #pragma unroll 1
-    for (int ih = 0; ih < nh; ++ih) {
-        const int h = hels[ih];
+    for (int it = 0; it < passes; ++it) {
+        const int ih_raw = grp + (it << lg);
+        const bool used = ih_raw < nh;
+        const int h = hels[used ? ih_raw : nh - 1];
         for (int e = threadIdx.x; e < P::ncol * 2 * ME_TILE; e += ME_TILE * P::waves) Jt[e] = 0.0;
         __syncthreads();
         coop_externals<P, double>(x, h, wave);
         P::template amps_wave<double>(x, Jl, nullptr, fm0, fm1, wsel);
         __syncthreads();
-        const double q = coop_colour<P, 0>(wave, Jl);
-        acc += q;
-        if (qhel) {  // uniform: a kernel argument
-            part[threadIdx.x] = q;
-            __syncthreads();
-            if (wave == 0 && valid) {
-                double s = 0.0;
-                for (int w = 0; w < P::waves; ++w) s += part[w * ME_TILE + lane];
-                qhel[ev * P::nhel + h] = s / P::lcd;
+        if constexpr (CM) {
+            static_assert(P::waves == 4, "one 16-column block of the tile per wave");
+            // Q of column c = 16 wave + lane % 16, whose helicity pass may differ from this lane's
+            const int col = 16 * wave + (lane & 15);
+            const bool col_used = (col & ((1 << lg) - 1)) + (it << lg) < nh;
+            const double q =
+                colour_mfma_group_sum(colour_mfma16<P::ncol>(Jt, 16 * wave, colour_table<P>::mfma_frag(), lane));
+            acc += col_used ? q : 0.0;
+            if (qhel) {
+                if (lane < 16) part[col] = q;
+                __syncthreads();
+                if (wave == 0 && valid && used) qhel[ev * P::nhel + h] = part[lane] / P::lcd;
+            }
+        } else {
+            const double q = coop_colour<P, 0>(wave, Jl);
+            acc += used ? q : 0.0;
+            if (qhel) {  // uniform: a kernel argument
+                part[threadIdx.x] = q;
+                __syncthreads();
+                if (wave == 0 && valid && used) {
+                    double s = 0.0;
+                    for (int w = 0; w < P::waves; ++w) s += part[w * ME_TILE + lane];
+                    qhel[ev * P::nhel + h] = s / P::lcd;
+                }
             }
         }
         __syncthreads();
     }
-    part[threadIdx.x] = acc;
+    if constexpr (CM) {
+        if (lane < 16) part[16 * wave + lane] = acc;  // the wave's columns, complete
+    } else {
+        part[threadIdx.x] = acc;  // this wave's share of every column
+    }
     __syncthreads();
-    if (wave == 0 && valid) {
+    if (wave == 0) {  // all 64 lanes of wave 0 take part in the group sum
         double s = 0.0;
-        for (int w = 0; w < P::waves; ++w) s += part[w * ME_TILE + lane];
-        out[ev] = s * (1.0 / (256.0 * P::identical * P::lcd));
+        if constexpr (CM) {
+            s = part[lane];
+        } else {
+            for (int w = 0; w < P::waves; ++w) s += part[w * ME_TILE + lane];
+        }
+        s = group_sum(s, lg);
+        if (valid && grp == 0) out[ev] = s * (1.0 / (256.0 * P::identical * P::lcd));
     }
 }

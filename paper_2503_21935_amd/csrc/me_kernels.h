@@ -7,6 +7,7 @@
 // matrix-element step of the paper, Sec. 2-3).  The result is averaged over
 // initial spins and colours and divided by the identical-particle factor.
 #pragma once
+#include "me_colour_mfma.h"
 #include "me_launch.h"
 
 template <int NPART>
@@ -83,16 +84,31 @@ MEV void gg_setup(gg_ext<T, P::ngluon>& x, const double* __restrict__ mom, int64
     x.gT = T(prm.gs);
 }
 
+// Sum of v over the 2^lg adjacent lanes that share an event (lanes
+// e 2^lg .. e 2^lg + 2^lg - 1); every lane of the group receives the sum.
+MEV double group_sum(double v, int lg) {
+#pragma unroll 1
+    for (int off = (1 << lg) >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // qhel (optional): per-helicity J^dag C J, [nevt][P::nhel], for the helicity
 // filter and for tests; entries of helicities not in the list are untouched.
 // idx (optional): evaluate only events idx[0..*count) (the float64 rerun of
 // events flagged by the mixed-precision kernel); out is indexed the same way.
+// lg: helicity parallelism, 2^lg lanes per event (0 <= lg <= 6): lane
+// g = lane % 2^lg of an event takes the helicities ih = g, g + 2^lg, ... of
+// the list, and the group's partial sums are added across its lanes at the
+// end, so a block of 64 lanes holds 64 / 2^lg events (the paper's
+// helicity-level parallelism, Sec. 2: fewer events in flight fill the GPU).
 template <class P>
 __global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ mom, int64_t nevt,
                                                     double* __restrict__ out, const int* __restrict__ hels,
                                                     int nh, me_params prm, double* __restrict__ qhel,
-                                                    const int* __restrict__ idx, const int* __restrict__ count) {
-    int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const int* __restrict__ idx, const int* __restrict__ count,
+                                                    int lg) {
+    const int grp = threadIdx.x & ((1 << lg) - 1);
+    int64_t ev = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg;
     if (count) {
         if (ev >= *count) return;
         ev = idx[ev];
@@ -107,7 +123,7 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ m
     gg_setup<P, T>(x, mom, ev, Qt, threadIdx.x, prm);
     T acc = T(0);
 #pragma unroll 1
-    for (int ih = 0; ih < nh; ++ih) {
+    for (int ih = grp; ih < nh; ih += 1 << lg) {
         const int h = hels[ih];
         // The momenta are read from LDS where they are used: the
         // helicity-independent subexpressions are recomputed per helicity
@@ -121,15 +137,80 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_gg(const double* __restrict__ m
         if (qhel) qhel[ev * P::nhel + h] = double(q) / P::lcd;
         acc += q;
     }
-    out[ev] = double(acc) * (1.0 / (256.0 * P::identical * P::lcd));
+    // the lanes of one event are all valid or all returned above
+    const double tot = group_sum(double(acc), lg);
+    if (grp == 0) out[ev] = tot * (1.0 / (256.0 * P::identical * P::lcd));
+}
+
+// The same evaluation with the colour sum on the matrix cores: after each
+// helicity's program the wave stages its 64 lanes' J in LDS as
+// [flow][re, im][lane] and the four 16-lane column blocks go through
+// colour_mfma16 (float64 MFMA GEMM, me_colour_mfma.h).  The MFMA needs all 64
+// lanes, so lanes past the end repeat the last event (no store) and every
+// lane makes the same number of helicity passes.
+template <class P>
+__global__ __launch_bounds__(ME_BLOCK) void k_me_gg_cm(const double* __restrict__ mom, int64_t nevt,
+                                                       double* __restrict__ out, const int* __restrict__ hels,
+                                                       int nh, me_params prm, double* __restrict__ qhel,
+                                                       const int* __restrict__ idx, const int* __restrict__ count,
+                                                       int lg) {
+    const int lane = threadIdx.x;
+    const int grp = lane & ((1 << lg) - 1);
+    const int64_t n = count ? (int64_t)*count : nevt;
+    const int64_t first = ((int64_t)blockIdx.x * ME_BLOCK) >> lg;
+    if (first >= n) return;  // the whole block
+    int64_t i = first + (lane >> lg);
+    const bool valid = i < n;
+    if (!valid) i = n - 1;
+    const int64_t ev = count ? (int64_t)idx[i] : i;
+    using T = double;
+    constexpr int NG = P::ngluon;
+    static_assert(ME_BLOCK == 64, "one wave per block");
+    __shared__ double Qt[ME_MOM_ROW(NG + 2)];
+    __shared__ double Jt[P::ncol * 2 * ME_BLOCK];
+    const double* frag = colour_table<P>::mfma_frag();
+    gg_ext<T, NG> x;
+    gg_setup<P, T>(x, mom, ev, Qt, lane, prm);
+    T acc = T(0);
+    const int passes = (nh + (1 << lg) - 1) >> lg;
+#pragma unroll 1
+    for (int it = 0; it < passes; ++it) {
+        const int ih = grp + (it << lg);
+        const bool used = ih < nh;
+        const int h = hels[used ? ih : nh - 1];
+        gg_externals<P, T>(x, h);
+        cx<T> J[P::ncol];
+#pragma unroll
+        for (int k = 0; k < P::ncol; ++k) J[k] = mk(T(0), T(0));
+        P::template amps<T>(x, J);
+        __syncthreads();  // the previous pass's reads of Jt are done
+#pragma unroll
+        for (int k = 0; k < P::ncol; ++k) {
+            Jt[(2 * k) * ME_BLOCK + lane] = J[k].r;
+            Jt[(2 * k + 1) * ME_BLOCK + lane] = J[k].i;
+        }
+        __syncthreads();
+        T q = T(0);
+#pragma unroll
+        for (int eb = 0; eb < 4; ++eb) {
+            const double p = colour_mfma_group_sum(colour_mfma16<P::ncol>(Jt, 16 * eb, frag, lane));
+            if (eb == (lane >> 4)) q = p;  // this lane's own column
+        }
+        if (qhel && valid && used) qhel[ev * P::nhel + h] = double(q) / P::lcd;
+        acc += used ? q : T(0);
+    }
+    const double tot = group_sum(double(acc), lg);
+    if (valid && grp == 0) out[ev] = tot * (1.0 / (256.0 * P::identical * P::lcd));
 }
 
 template <class P>
 __global__ __launch_bounds__(ME_BLOCK) void k_me_ee(const double* __restrict__ mom, int64_t nevt,
                                                     double* __restrict__ out, const int* __restrict__ hels,
                                                     int nh, me_params prm, double* __restrict__ qhel,
-                                                    const int* __restrict__ idx, const int* __restrict__ count) {
-    int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const int* __restrict__ idx, const int* __restrict__ count,
+                                                    int lg) {
+    const int grp = threadIdx.x & ((1 << lg) - 1);
+    int64_t ev = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg;
     if (count) {
         if (ev >= *count) return;
         ev = idx[ev];
@@ -140,11 +221,12 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_ee(const double* __restrict__ m
     mom4<T> p[P::npart];
     load_event<T, P::npart>(mom, ev, p);
     T acc = T(0);
-    for (int ih = 0; ih < nh; ++ih) {
+    for (int ih = grp; ih < nh; ih += 1 << lg) {
         const int h = hels[ih];
         const T q = P::template me_hel<T>(p, h, prm);
         if (qhel) qhel[ev * P::nhel + h] = double(q);
         acc += q;
     }
-    out[ev] = double(acc) * 0.25;
+    const double tot = group_sum(double(acc), lg);
+    if (grp == 0) out[ev] = tot * 0.25;
 }

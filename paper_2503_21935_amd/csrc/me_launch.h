@@ -8,8 +8,9 @@
 
 #define ME_BLOCK 64
 
+// lg: 2^lg lanes per event, each summing every 2^lg-th helicity (0 <= lg <= 6).
 typedef hipError_t (*me_launch_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
-                                   const me_params& prm, double* qhel, hipStream_t stream);
+                                   const me_params& prm, double* qhel, int lg, hipStream_t stream);
 
 // Indexed variant: evaluate events idx[0..*count) only (count on the device).
 typedef hipError_t (*me_launch_idx_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
@@ -29,12 +30,14 @@ struct me_process_desc {
     const char* name;
     int kind;
     int npart, ndiag, ncol, nhel;
-    double flops_amp, flops_colour;  // per helicity
+    double flops_amp, flops_colour;  // per helicity, algorithmic
+    double flops_executed;           // per helicity, as the kernel executes it (recomputation included)
     me_launch_fn launch_f64;
     me_launch_idx_fn launch_f64_idx;
     me_launch_mixed_fn launch_mixed;  // nullptr: the process has no mixed form
     double mixed_cest;                // calibration of the amplitude error estimate
     double colour_err;                // a-priori error of the float16 hi/lo colour sum
+    me_launch_fn launch_f64_cm;       // float64 with the colour sum on the matrix cores (nullptr: none)
 };
 
 const me_process_desc* me_find_process(const char* name);

@@ -63,6 +63,7 @@ struct proc_ee_mumu {
     // external spinors 4 x 40, two split currents 2 x 72, contraction and propagators
     static constexpr double flops_amp = 4 * 40 + 2 * 72 + 4 * 30 + 16 + 60;
     static constexpr double flops_colour = 3;
+    static constexpr double flops_executed = flops_amp;  // no shared wavefunctions to recompute
     static constexpr int n_amplitudes = 2;
     static constexpr int ndiag = 2;
 

@@ -88,3 +88,22 @@ def colour_matrix_exact(n: int):
     lcd = reduce(lambda a, b: a * b // math.gcd(a, b), (c.denominator for row in C for c in row), 1)
     num = [[int(c * lcd) for c in row] for row in C]
     return num, lcd
+
+
+def mfma_fragments(num):
+    """First-operand fragments of v_mfma_f64_16x16x4f64 for the blocked
+    symmetric colour GEMM: flows in blocks of 16 (padded with zeros), block
+    pairs I <= J numbered J (J + 1) / 2 + I, four K steps of 4 flows each.
+    Entry [(pair * 4 + ks) * 64 + l] = w_IJ N[16 J + l % 16][16 I + 4 ks + l // 16]
+    with w_II = 1, w_IJ = 2 (I < J), 0 outside N."""
+    nc = len(num)
+    nb = (nc + 15) // 16
+    out = []
+    for jb in range(nb):
+        for ib in range(jb + 1):
+            w = 1 if ib == jb else 2
+            for ks in range(4):
+                for l in range(64):
+                    j, k = 16 * jb + l % 16, 16 * ib + 4 * ks + l // 16
+                    out.append(w * num[j][k] if (j < nc and k < nc) else 0)
+    return out

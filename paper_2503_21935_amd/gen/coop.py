@@ -503,6 +503,12 @@ class GGCoopEmitter(GGEmitter):
         for row in fmaps:
             h.append("    " + ", ".join(map(str, row)) + ",")
         h.append("};")
+        from .emit import emit_mfma_table
+
+        h.extend(emit_mfma_table(self.name, self.num))
+        h.append(f"template <> struct colour_table<proc_{self.name}> {{")
+        h.append(f"    static MEV const double* mfma_frag() {{ return colour_mfma_{self.name}; }}")
+        h.append("};")
         h.append(f"template <> struct coop_table<proc_{self.name}> {{")
         h.append(f"    static MEV const int* fmap(int w) {{ return coop_fmap_{self.name} + w * {nc}; }}")
         h.append(f"    static MEV const unsigned int* bfrag() {{ return coop_bfrag_{self.name}; }}")

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import math
 
-from .colour import colour_matrix_exact, orderings
+from .colour import colour_matrix_exact, mfma_fragments, orderings
 from .diagrams import count_feynman_diagrams
 from .plan import Plan
 
@@ -36,6 +36,17 @@ def _coef_ops(c):
     if c == 1j:
         return "add_i"
     return "sub_i"
+
+
+def emit_mfma_table(name, num):
+    """The N fragments of the float64 matrix-core colour sum (colour.mfma_fragments)."""
+    frag = mfma_fragments(num)
+    out = [f"// float64 MFMA colour fragments, [block pair][K step][lane], weights 1 (diagonal) / 2 folded in",
+           f"__device__ static const double colour_mfma_{name}[{len(frag)}] = {{"]
+    for i in range(0, len(frag), 16):
+        out.append("    " + ", ".join(f"{v}.0" for v in frag[i:i + 16]) + ",")
+    out.append("};")
+    return out
 
 
 class GGEmitter:
@@ -566,7 +577,9 @@ class GGEmitter:
         for row in self.num:
             h.append("    " + ", ".join(str(v) for v in row) + ",")
         h.append("};")
+        h.extend(emit_mfma_table(self.name, self.num))
         h.append(f"template <> struct colour_table<proc_{self.name}> {{")
         h.append(f"    static MEV int get(int k, int l) {{ return colour_num_{self.name}[k * {nc} + l]; }}")
+        h.append(f"    static MEV const double* mfma_frag() {{ return colour_mfma_{self.name}; }}")
         h.append("};")
         return "\n".join(h) + "\n"

@@ -46,23 +46,32 @@ def emulated_forward(theta, x, keep=False):
     return (y, zs, hs) if keep else y
 
 
-def emulated_grad(theta, x, t):
+def emulated_grad(theta, x, t, magnitudes=False):
+    """Gradient with the kernels' BF16 roundings; with magnitudes=True also the
+    sums of |terms| behind every entry (the scale of its rounding error)."""
     y, zs, hs = emulated_forward(theta, x, keep=True)
     layers, w_out, _ = R.unpack(theta)
     m = len(t)
     dy = 2 * (y - t) / m
-    g_layers = [None] * len(layers)
+    g_layers, a_layers = [None] * len(layers), [None] * len(layers)
     g_wout = hs[-1].T @ dy
+    a_wout = np.abs(hs[-1]).T @ np.abs(dy)
     g_bout = np.array([dy.sum()])
+    a_bout = np.array([np.abs(dy).sum()])
     dz = R.bf16_round(np.outer(dy, w_out) * R.silu_prime(zs[-1]))
     for l in range(len(layers) - 1, -1, -1):
         g_layers[l] = (dz.T @ hs[l], dz.sum(axis=0))
+        a_layers[l] = (np.abs(dz).T @ np.abs(hs[l]), np.abs(dz).sum(axis=0))
         if l > 0:
             dz = R.bf16_round((dz @ R.bf16_round(layers[l][0])) * R.silu_prime(zs[l - 1]))
-    parts = []
-    for gW, gb in g_layers:
+    parts, amag = [], []
+    for (gW, gb), (aW, ab) in zip(g_layers, a_layers):
         parts += [gW.ravel(), gb]
-    return np.concatenate(parts + [g_wout, g_bout])
+        amag += [aW.ravel(), ab]
+    g = np.concatenate(parts + [g_wout, g_bout])
+    if magnitudes:
+        return g, np.concatenate(amag + [a_wout, a_bout])
+    return g
 
 
 def features_np(mom):
@@ -118,6 +127,70 @@ def test_backward_matches_reference(me_mod, torch_cuda):
         assert rel < 1e-2, (a, b, rel)
         assert rel_x < 5e-2, (a, b, rel_x)
     print(f"[mlp] backward: worst tensor vs BF16-emulating reference {worst:.2e}", flush=True)
+    net.close()
+
+
+def test_forward_elementwise(me_mod, torch_cuda):
+    """Every sample's output against the BF16-emulating reference, within 2^-6
+    of the sum of the magnitudes of the output layer's terms for that sample
+    (a flipped BF16 rounding of an activation moves it by at most 2^-8 of
+    itself; a wrong row or column of any layer moves whole outputs by O(1))."""
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=16)
+    theta = net.get_params().astype(np.float64)
+    x = features_np(process_points("gg_ttgg", 2111, 4))
+    y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+    emu, zs, hs = emulated_forward(theta, x.astype(np.float64), keep=True)
+    _, w_out, b_out = R.unpack(theta)
+    scale = np.abs(hs[-1]) @ np.abs(w_out) + abs(b_out[0])
+    ratio = np.abs(y - emu) / scale
+    print(f"[mlp] forward per sample: max |y - emu| / scale {ratio.max():.2e}, median {np.median(ratio):.2e}",
+          flush=True)
+    assert ratio.max() < 2.0 ** -6
+    net.close()
+
+
+def test_backward_elementwise(me_mod, torch_cuda):
+    """Every gradient entry against the BF16-emulating reference, within 2^-5 of
+    the sum of the magnitudes of the batch terms that make up that entry."""
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=17)
+    theta = net.get_params().astype(np.float64)
+    x = features_np(process_points("gg_ttgg", 1024, 9))
+    t = np.random.default_rng(9).normal(size=1024).astype(np.float32)
+    g, _ = net.backward(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda())
+    g = g.cpu().numpy().astype(np.float64)
+    ge, mag = emulated_grad(theta, x.astype(np.float64), t.astype(np.float64), magnitudes=True)
+    ratio = np.abs(g - ge) / np.maximum(mag, 1e-30)
+    worst = int(np.argmax(ratio))
+    print(f"[mlp] backward per entry: max |g - emu| / magnitude {ratio.max():.2e} (entry {worst}), "
+          f"median {np.median(ratio):.2e}", flush=True)
+    assert ratio.max() < 2.0 ** -5
+    net.close()
+
+
+def test_adam_three_steps(me_mod, torch_cuda):
+    """Three consecutive training steps on a fixed batch against the CPU Adam
+    fed the same gradients (taken from the GPU's own backward pass at each
+    step): exercises the step counter and the bias correction beyond t = 1."""
+    torch = torch_cuda
+    net = me_mod.Surrogate(seed=18)
+    theta = net.get_params().astype(np.float64)
+    x = torch.from_numpy(features_np(process_points("gg_ttgg", 512, 10))).cuda()
+    t = torch.from_numpy(np.random.default_rng(10).normal(size=512).astype(np.float32)).cuda()
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    lrs = [1e-3, 7e-4, 4e-4]
+    for step, lr in enumerate(lrs, start=1):
+        g, _ = net.backward(x, t)  # the gradient train_step computes at the current weights
+        g = g.cpu().numpy().astype(np.float64)
+        net.train_step(x, t, None, lr)
+        torch.cuda.synchronize()
+        theta, m, v = R.adam_step(theta, m, v, g, step, lr)
+        got = net.get_params().astype(np.float64)
+        # float32 master weights: the update itself is computed to ~1e-7 of lr
+        np.testing.assert_allclose(got, theta, rtol=0, atol=2e-6 * lr + 2e-7, err_msg=f"step {step}")
+        theta = got  # continue from the GPU's float32 weights
     net.close()
 
 

@@ -208,6 +208,63 @@ def test_empty_and_errors(me_mod, torch_cuda):
     assert e.value.status == me_mod.ME_EINVAL
 
 
+@pytest.mark.parametrize("proc,lanes,n", [("gg_ttgg", 4, 131), ("gg_ttgg", 64, 77), ("gg_ttgg", 2, 1),
+                                          ("gg_tt", 16, 1000), ("ee_mumu", 4, 999), ("ee_mumu", 64, 5),
+                                          ("gg_ttg", 8, 200), ("gg_ttggg", 4, 21), ("gg_ttggg", 64, 3)])
+def test_helicity_lanes(me_mod, torch_cuda, proc, lanes, n):
+    """Helicity-level parallelism (2^k lanes per event): equal to the one-lane
+    result up to the order of the helicity sum, and parity-green, at ragged sizes."""
+    torch = torch_cuda
+    print(f"[lanes] {proc} lanes={lanes} n={n}", flush=True)
+    mom = process_points(proc, n, 41)
+    t = torch.from_numpy(mom).cuda()
+    m = me_mod.MatrixElement(proc)
+    one = m.eval(t)
+    m.set_helicity_lanes(lanes)
+    many = m.eval(t)
+    torch.cuda.synchronize()
+    one, many = one.cpu().numpy(), many.cpu().numpy()
+    np.testing.assert_allclose(many, one, rtol=1e-13, atol=0)
+    check_parity(proc, mom, many)
+    with pytest.raises(me_mod.MEError) as e:
+        m.set_helicity_lanes(3)
+    assert e.value.status == me_mod.ME_EINVAL
+    m.close()
+
+
+@pytest.mark.parametrize("proc,lanes,n", [("gg_ttgg", 1, 131), ("gg_ttgg", 4, 70), ("gg_ttgg", 1, 1),
+                                          ("gg_ttggg", 1, 67), ("gg_ttggg", 8, 9)])
+def test_colour_on_matrix_cores(me_mod, torch_cuda, proc, lanes, n):
+    """The float64 colour sum as a batched MFMA GEMM over block pairs of the
+    symmetric colour matrix: equal to the VALU form up to rounding, parity-green
+    per event and per helicity, at ragged sizes and with helicity lanes."""
+    torch = torch_cuda
+    print(f"[colour-mfma] {proc} lanes={lanes} n={n}", flush=True)
+    mom = process_points(proc, n, 43)
+    t = torch.from_numpy(mom).cuda()
+    m = me_mod.MatrixElement(proc)
+    valu = m.eval(t)
+    m.set_colour_form(me_mod.ME_COLOUR_MFMA)
+    m.set_helicity_lanes(lanes)
+    mf = m.eval(t)
+    torch.cuda.synchronize()
+    valu, mf = valu.cpu().numpy(), mf.cpu().numpy()
+    np.testing.assert_allclose(mf, valu, rtol=1e-13, atol=0)
+    check_parity(proc, mom, mf)
+    k = min(n, 4)
+    me2, qh = m.eval_helicities(t[:k])
+    torch.cuda.synchronize()
+    want_me2, want_qh = oracle.me2(proc, mom[:k], per_helicity=True)
+    scale = want_qh.max(axis=1, keepdims=True)
+    np.testing.assert_allclose(qh.cpu().numpy() / scale, want_qh / scale, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(me2.cpu().numpy(), want_me2, rtol=1e-12)
+    m.close()
+    g = get_me(me_mod, "gg_tt")
+    with pytest.raises(me_mod.MEError) as e:
+        g.set_colour_form(me_mod.ME_COLOUR_MFMA)
+    assert e.value.status == me_mod.ME_ESTATE
+
+
 def test_binding_refuses_short_buffers(me_mod, torch_cuda):
     """Buffers shorter than the call touches are refused before the C call."""
     torch = torch_cuda
