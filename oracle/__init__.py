@@ -75,7 +75,13 @@ def _lib(quad: bool = False):
     lib.oracle_ggx.argtypes = [dp, ctypes.c_int64, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, dp, dp]
     lib.oracle_ggx_amps.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                    ctypes.c_double, ctypes.c_double, dp]
+                                    ctypes.c_double, ctypes.c_double, dp, ctypes.c_int]
+    lib.oracle_ggx_diagram_amps.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, dp]
+    lib.oracle_ggx_diagrams.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, dp]
     lib.oracle_ggx_dressed.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        dp, dp]
     return lib
@@ -182,12 +188,16 @@ def me2(process: str, mom, params=None, quad: bool = False, per_helicity: bool =
     return (out, qh) if per_helicity else out
 
 
-def ordered_amps(n: int, mom1, hel: int, params=None, gauge_gluon: int = -1, quad: bool = False):
-    """Colour-ordered partial amplitudes J[k] (k over ``orderings(n)``) of one event."""
+def ordered_amps(n: int, mom1, hel: int, params=None, gauge_gluon: int = -1, quad: bool = False,
+                 four_gluon: bool = True):
+    """Colour-ordered partial amplitudes J[k] (k over ``orderings(n)``) of one event.
+    four_gluon=False leaves the four-gluon vertex out of the recursion: the sum
+    over the ordered diagrams built from three-point vertices only."""
     p = params or sm_params()
     mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(n + 2, 4)
     out = np.empty((math.factorial(n), 2))
-    rc = _lib(quad).oracle_ggx_amps(_ptr(mom1), n, hel, gauge_gluon, p["gs"], p["mt"], p["wt"], _ptr(out))
+    rc = _lib(quad).oracle_ggx_amps(_ptr(mom1), n, hel, gauge_gluon, p["gs"], p["mt"], p["wt"], _ptr(out),
+                                    int(four_gluon))
     if rc != 0:
         raise RuntimeError("oracle failed")
     return out[:, 0] + 1j * out[:, 1]
@@ -203,6 +213,120 @@ def me2_dressed(n: int, mom1, params=None, per_helicity: bool = False):
     if rc != 0:
         raise RuntimeError("oracle failed")
     return (out[0], qh) if per_helicity else out[0]
+
+
+# --------------------------------------------------------------------------
+# Single Feynman diagrams (route 4): the multi-channel weights
+# --------------------------------------------------------------------------
+
+_MAXG = 5
+_DIAG_STRIDE = 2 + _MAXG + 3 * 2 * _MAXG
+
+
+def _trees(S):
+    """Binary gluon trees over the set S (three-gluon vertices only), as nested
+    tuples; the subtree holding the smallest label comes first."""
+    S = tuple(sorted(S))
+    if len(S) == 1:
+        return [S[0]]
+    first, rest = S[0], S[1:]
+    out = []
+    for k in range(0, len(rest)):
+        for extra in itertools.combinations(rest, k):
+            A = (first,) + extra
+            B = tuple(x for x in rest if x not in extra)
+            if not B:
+                continue
+            for ta in _trees(A):
+                for tb in _trees(B):
+                    out.append((ta, tb))
+    return out
+
+
+def _ordered_set_partitions(items):
+    items = tuple(items)
+    if not items:
+        yield ()
+        return
+    for k in range(1, len(items) + 1):
+        for first in itertools.combinations(items, k):
+            rest = tuple(x for x in items if x not in first)
+            for tail in _ordered_set_partitions(rest):
+                yield (first,) + tail
+
+
+def _tree_desc(t):
+    if isinstance(t, int):
+        return str(t)
+    return "(" + _tree_desc(t[0]) + "," + _tree_desc(t[1]) + ")"
+
+
+def channel_diagrams(n: int):
+    """Every Feynman diagram of g g -> t tbar + (n-2) g whose gluons meet only
+    at three-point vertices: the channels of the multi-channel weights.  A
+    diagram is a sequence of gluon trees attached along the top line from
+    ubar(p3) to v(p4).  Returns (descriptors, encoding [ndiag][stride] int32);
+    a descriptor writes the trees in top-line order separated by '|', a tree
+    as nested '(x,y)' with the part holding the smaller label first."""
+    descs, rows = [], []
+    for part in _ordered_set_partitions(range(n)):
+        for trees in itertools.product(*(_trees(B) for B in part)):
+            nodes, roots = [], []
+
+            def emit(t):
+                if isinstance(t, int):
+                    nodes.append((-1, -1, t))
+                else:
+                    l = emit(t[0])
+                    r = emit(t[1])
+                    nodes.append((l, r, -1))
+                return len(nodes) - 1
+
+            for t in trees:
+                roots.append(emit(t))
+            row = np.zeros(_DIAG_STRIDE, dtype=np.int32)
+            row[0] = len(roots)
+            row[1:1 + len(roots)] = roots
+            row[1 + _MAXG] = len(nodes)
+            for i, (l, r, leaf) in enumerate(nodes):
+                row[2 + _MAXG + 3 * i: 2 + _MAXG + 3 * i + 3] = (l, r, leaf)
+            rows.append(row)
+            descs.append("|".join(_tree_desc(t) for t in trees))
+    return descs, np.stack(rows)
+
+
+def diagram_amps(n: int, mom1, hel: int, params=None):
+    """Complex amplitudes A_d of every channel diagram (order of
+    channel_diagrams) of one event at one helicity."""
+    p = params or sm_params()
+    mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(n + 2, 4)
+    descs, enc = channel_diagrams(n)
+    enc = np.ascontiguousarray(enc)
+    out = np.empty((len(descs), 2))
+    rc = _lib(False).oracle_ggx_diagram_amps(_ptr(mom1), n, hel, len(descs),
+                                             enc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), p["gs"], p["mt"],
+                                             p["wt"], _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return descs, out[:, 0] + 1j * out[:, 1]
+
+
+def diagram_sums(process: str, mom, params=None):
+    """sum over all helicities of |A_d|^2 for every channel diagram d of the
+    process (order of channel_diagrams), per event: [nevt][ndiag]."""
+    p = params or sm_params()
+    ng = PROCESS_NGLUON[process]
+    mom = _check_mom(mom, ng + 2)
+    descs, enc = channel_diagrams(ng)
+    enc = np.ascontiguousarray(enc)
+    out = np.empty((mom.shape[0], len(descs)))
+    lib = _lib(False)
+    rc = lib.oracle_ggx_diagrams(_ptr(mom), mom.shape[0], ng, len(descs),
+                                 enc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), p["gs"], p["mt"], p["wt"],
+                                 _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return descs, out
 
 
 # --------------------------------------------------------------------------

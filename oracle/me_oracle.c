@@ -389,7 +389,7 @@ static void v3(const cplx X[4], const real QX[4], const cplx Y[4], const real QY
  *                                   - g^{mu sig} g^{nu rho}] (X, Y, Z, root)
  * Gluon currents include the propagator -i/Q^2.
  */
-static void bg_amp(const ggx_ext *X, const int *sigma, cplx *out_amp) {
+static void bg_amp(const ggx_ext *X, const int *sigma, cplx *out_amp, int with4) {
     int n = X->n;
     real g = X->gs;
     cplx J[MAXG][MAXG][4];
@@ -412,7 +412,7 @@ static void bg_amp(const ggx_ext *X, const int *sigma, cplx *out_amp) {
                 /* (-i/Q^2)(-i g) = -g/Q^2 */
                 for (int mu = 0; mu < 4; ++mu) acc[mu] += (-g / Q2) * t[mu];
             }
-            for (int k = i; k < j; ++k)
+            for (int k = i; k < j && with4; ++k)
                 for (int l = k + 1; l < j; ++l) {
                     const cplx *A = J[i][k], *B = J[k + 1][l], *C = J[l + 1][j];
                     cplx ac = cdot(A, C), ab = cdot(A, B), bc = cdot(B, C);
@@ -473,13 +473,13 @@ static int factorial(int n) { return n <= 1 ? 1 : n * factorial(n - 1); }
 
 /* Partial amplitudes J[k] for all n! orderings (lexicographic order of
  * permutations of gluon indices 0..n-1) at one helicity. */
-static void ordered_amps(const ggx_ext *X, cplx *J) {
+static void ordered_amps(const ggx_ext *X, cplx *J, int with4) {
     int n = X->n;
     int sigma[MAXG];
     for (int i = 0; i < n; ++i) sigma[i] = i;
     int k = 0;
     do {
-        bg_amp(X, sigma, &J[k++]);
+        bg_amp(X, sigma, &J[k++], with4);
     } while (next_perm(sigma, n));
 }
 
@@ -506,7 +506,7 @@ static real ggx_one(const real *mom, int n, const real *C, real gs, real mt, rea
     for (int h = 0; h < (1 << np); ++h) {
         ggx_ext X;
         ggx_setup(mom, n, h, -1, gs, mt, wt, &X);
-        ordered_amps(&X, J);
+        ordered_amps(&X, J, 1);
         real q = colour_form(J, C, ncol);
         if (qhel) qhel[h] = q;
         total += q;
@@ -537,7 +537,7 @@ int oracle_ggx(const double *mom, int64_t nevt, int n, const double *colour, dou
 /* Partial amplitudes of one event at one helicity, for gauge and MHV checks.
  * out: [n!][2] (re, im). */
 int oracle_ggx_amps(const double *mom1, int n, int h, int gauge_gluon, double gs, double mt, double wt,
-                    double *out) {
+                    double *out, int with4) {
     if (!mom1 || !out || n < 2 || n > MAXG) return -1;
     int np = n + 2, ncol = factorial(n);
     real m[4 * MAXNP];
@@ -545,7 +545,7 @@ int oracle_ggx_amps(const double *mom1, int n, int h, int gauge_gluon, double gs
     ggx_ext X;
     ggx_setup(m, n, h, gauge_gluon, gs, mt, wt, &X);
     cplx *J = (cplx *)malloc(sizeof(cplx) * ncol);
-    ordered_amps(&X, J);
+    ordered_amps(&X, J, with4);
     for (int k = 0; k < ncol; ++k) {
         out[2 * k] = (double)CREAL(J[k]);
         out[2 * k + 1] = (double)CIMAG(J[k]);
@@ -800,4 +800,117 @@ int oracle_is_quad(void) {
 #else
     return 0;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Route 4: single Feynman diagrams (three-point vertices only)          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The multi-channel weights of the paper's Sec. 2 need the squared amplitude
+ * of each single Feynman diagram, summed over helicities.  Here a diagram is
+ * a sequence of gluon trees attached along the top line from ubar(p3) to
+ * v(p4); each tree is built from three-gluon vertices only (diagrams with a
+ * four-gluon vertex are not channels).  With the colour factors stripped so
+ * that every colour-flow coefficient has unit modulus (f^{abc} T^c =
+ * -i [T^a, T^b], the quark-gluon vertex T^a), the kinematic amplitude is
+ *   A = ubar(p3) (i g Wslash_1) S(P_1) (i g Wslash_2) ... (i g Wslash_j) v(p4),
+ *   P_i = p3 - (sum of the incoming-flow momenta of trees 1..i),
+ * with the tree currents W = eps for a leaf and
+ *   W(X, Y) = (-i / Q^2)(-i g) V(Q_X, Q_Y, -Q_X - Q_Y) . W_X W_Y
+ * for a vertex joining subtrees X and Y (the order of X and Y only flips the
+ * sign).  |A|^2 does not depend on spinor or polarisation phase conventions.
+ *
+ * A diagram is encoded as ints: [nblocks, root node of each block (MAXG
+ * slots), nnodes, then per node (left, right, leaf)], leaf >= 0 for an
+ * external gluon (left = right = -1), otherwise left/right are earlier nodes.
+ */
+#define DIAG_STRIDE (2 + MAXG + 3 * 2 * MAXG)
+
+static cplx diagram_amp(const ggx_ext *X, const int *d) {
+    const int nb = d[0];
+    const int *root = d + 1;
+    const int nn = d[1 + MAXG];
+    const int *node = d + 2 + MAXG;
+    real g = X->gs;
+    cplx W[2 * MAXG][4];
+    real Q[2 * MAXG][4];
+    for (int i = 0; i < nn; ++i) {
+        const int l = node[3 * i], r = node[3 * i + 1], leaf = node[3 * i + 2];
+        if (leaf >= 0) {
+            for (int mu = 0; mu < 4; ++mu) {
+                W[i][mu] = X->eps[leaf][mu];
+                Q[i][mu] = X->q[leaf][mu];
+            }
+            continue;
+        }
+        for (int mu = 0; mu < 4; ++mu) Q[i][mu] = Q[l][mu] + Q[r][mu];
+        const real Q2 = rdot(Q[i], Q[i]);
+        cplx t[4];
+        v3(W[l], Q[l], W[r], Q[r], t);
+        for (int mu = 0; mu < 4; ++mu) W[i][mu] = (-g / Q2) * t[mu];
+    }
+    cplx U[4];
+    memcpy(U, X->ubar3, sizeof(U));
+    real P[4];
+    memcpy(P, X->p3, sizeof(P));
+    for (int b = 0; b < nb; ++b) {
+        const int k = root[b];
+        cplx js[4][4], t[4];
+        slash_c(W[k], js);
+        row_mat(U, js, t);
+        for (int a = 0; a < 4; ++a) U[a] = CI * g * t[a];
+        if (b + 1 < nb) {
+            for (int mu = 0; mu < 4; ++mu) P[mu] -= Q[k][mu];
+            cplx S[4][4];
+            fprop(P, X->mt, X->wt, S);
+            row_mat(U, S, t);
+            memcpy(U, t, sizeof(U));
+        }
+    }
+    return row_col(U, X->v4);
+}
+
+/* out[e][k] = sum over all helicities of |A_k|^2 for the ndiag diagrams in
+ * enc ([ndiag][DIAG_STRIDE]), and (optionally) me2-normalised: the same
+ * average over initial spins and colours as me2 is not applied (these are
+ * ratios). */
+int oracle_ggx_diagrams(const double *mom, int64_t nevt, int n, int ndiag, const int *enc, double gs, double mt,
+                        double wt, double *out) {
+    if (n < 2 || n > MAXG || ndiag < 1) return -1;
+    const int np = n + 2, nhel = 1 << np;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t e = 0; e < nevt; ++e) {
+        real p[4 * MAXNP];
+        for (int i = 0; i < 4 * np; ++i) p[i] = mom[e * 4 * np + i];
+        double *o = out + e * ndiag;
+        for (int k = 0; k < ndiag; ++k) o[k] = 0.0;
+        for (int h = 0; h < nhel; ++h) {
+            ggx_ext X;
+            ggx_setup(p, n, h, -1, gs, mt, wt, &X);
+            for (int k = 0; k < ndiag; ++k) {
+                const cplx a = diagram_amp(&X, enc + (int64_t)k * DIAG_STRIDE);
+                o[k] += (double)(CREAL(a) * CREAL(a) + CIMAG(a) * CIMAG(a));
+            }
+        }
+    }
+    return bad;
+}
+
+/* The complex amplitudes A_d of the ndiag encoded diagrams for one event at
+ * one helicity (for checks). */
+int oracle_ggx_diagram_amps(const double *mom1, int n, int h, int ndiag, const int *enc, double gs, double mt,
+                            double wt, double *out) {
+    if (!mom1 || !out || n < 2 || n > MAXG) return -1;
+    real m[4 * MAXNP];
+    for (int j = 0; j < 4 * (n + 2); ++j) m[j] = mom1[j];
+    ggx_ext X;
+    ggx_setup(m, n, h, -1, gs, mt, wt, &X);
+    for (int k = 0; k < ndiag; ++k) {
+        const cplx a = diagram_amp(&X, enc + (int64_t)k * DIAG_STRIDE);
+        out[2 * k] = (double)CREAL(a);
+        out[2 * k + 1] = (double)CIMAG(a);
+    }
+    return 0;
 }

@@ -17,3 +17,23 @@ def params():
     import oracle
 
     return oracle.sm_params()
+
+
+_ORACLE_CACHE = {}
+
+
+@pytest.fixture(scope="session")
+def oracle_points():
+    """(momenta, oracle |M|^2) of the first n seeded RAMBO points of a
+    workload, computed once per session (the oracle runs multi-threaded)."""
+    import oracle
+    from inputs import process_points
+
+    def get(proc, n, seed):
+        key = (proc, n, seed)
+        if key not in _ORACLE_CACHE:
+            mom = process_points(proc, n, seed)
+            _ORACLE_CACHE[key] = (mom, oracle.me2(proc, mom))
+        return _ORACLE_CACHE[key]
+
+    return get

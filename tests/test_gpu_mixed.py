@@ -33,12 +33,13 @@ def me_mod(torch_cuda):
     return me
 
 
-# g g -> t tbar g g g: the oracle takes about a second per event here
-@pytest.mark.parametrize("proc,n,seed", [("gg_tt", 65536, 1), ("gg_ttg", 8192, 7), ("gg_ttgg", 8192, 2),
-                                         ("gg_ttggg", 160, 3)])
-def test_mixed_within_tolerance(me_mod, torch_cuda, proc, n, seed):
+# g g -> t tbar g g g: the oracle's 2^12 events are shared with the float64 parity test
+@pytest.mark.parametrize("proc,n,seed", [("gg_tt", 65536, 1), ("gg_ttg", 8192, 7), ("gg_ttgg", 1 << 16, 2),
+                                         ("gg_ttggg", 1 << 12, 3)])
+def test_mixed_within_tolerance(me_mod, torch_cuda, oracle_points, proc, n, seed):
     torch = torch_cuda
-    mom = process_points(proc, n, seed)
+    print(f"[mixed] {proc} n={n} seed={seed}", flush=True)
+    mom, want = oracle_points(proc, n, seed)
     m = me_mod.MatrixElement(proc)
     m.set_precision(me_mod.ME_MIXED, TOL)
     t = torch.from_numpy(mom).cuda()
@@ -48,7 +49,6 @@ def test_mixed_within_tolerance(me_mod, torch_cuda, proc, n, seed):
     raw, est, flag = m.eval_mixed_diag(t)
     torch.cuda.synchronize()
     got, raw, est, flag = got.cpu().numpy(), raw.cpu().numpy(), est.cpu().numpy(), flag.cpu().numpy()
-    want = oracle.me2(proc, mom)
     rel = np.abs(got / want - 1)
     rel_raw = np.abs(raw / want - 1)
     print(f"[mixed] {proc}: fallback {nfb}/{n}; float32-form error p50 {np.median(rel_raw):.2e} "
@@ -57,8 +57,10 @@ def test_mixed_within_tolerance(me_mod, torch_cuda, proc, n, seed):
     assert nfb == int(flag.sum())
     assert np.all(np.isfinite(got))
     assert rel.max() <= TOL
-    # the estimate bounds the error of every event it lets through
+    # the calibrated estimate is above the error of every event it lets through
     ok = flag == 0
+    ratio = rel_raw[ok] / np.maximum(est[ok], 1e-300)
+    print(f"[mixed] {proc}: largest error / estimate over unflagged events {ratio.max():.2f}", flush=True)
     assert np.all(rel_raw[ok] <= np.maximum(est[ok], 0)), "estimate below the actual error"
     m.close()
 

@@ -12,6 +12,8 @@ float64 momenta themselves): such events are ill-conditioned, typically a top
 propagator close to its mass shell, and no float64 evaluation resolves them
 better than that spread.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -78,8 +80,9 @@ def input_sensitivity(proc, mom, nsamp=4):
     return q0, spread
 
 
-def check_parity(proc, mom, got, tol=TOL):
-    want = oracle.me2(proc, mom)
+def check_parity(proc, mom, got, tol=TOL, want=None):
+    if want is None:
+        want = oracle.me2(proc, mom)
     assert np.all(np.isfinite(got)), f"{proc}: non-finite GPU results"
     rel = np.abs(got / want - 1)
     bad = np.nonzero(rel > tol)[0]
@@ -172,6 +175,31 @@ def test_full_size_sampled_ggttggg(me_mod, torch_cuda):
     idx = np.concatenate([idx, [0, n - 1]])
     rel = check_parity("gg_ttggg", mom[idx], got[idx])
     print(f"[parity] gg_ttggg 2^18 sampled: max rel {rel.max():.2e}", flush=True)
+
+
+@pytest.mark.parametrize("proc,n,seed", [("gg_ttgg", 1 << 16, 2), ("gg_ttggg", 1 << 12, 3)])
+def test_parity_wide(me_mod, torch_cuda, oracle_points, proc, n, seed):
+    """The routine wide parity sets: the first 2^16 g g -> t tbar g g points of
+    the benchmark's seed and the first 2^12 g g -> t tbar g g g points, every
+    event against the oracle (run on all host cores)."""
+    print(f"[parity-wide] {proc} n={n} seed={seed}", flush=True)
+    mom, want = oracle_points(proc, n, seed)
+    got = gpu_me2(me_mod, torch_cuda, proc, mom)
+    rel = check_parity(proc, mom, got, want=want)
+    print(f"[parity-wide] {proc}: max rel {rel.max():.2e}, p99.9 {np.quantile(rel, 0.999):.2e}, "
+          f"median {np.median(rel):.2e}, beyond 1e-12: {int((rel > TOL).sum())}", flush=True)
+
+
+@pytest.mark.skipif(os.environ.get("ME_PARITY_FULL") != "1",
+                    reason="all 2^20 events against the oracle: minutes of host time, run with ME_PARITY_FULL=1")
+def test_parity_all_ggttgg(me_mod, torch_cuda):
+    """Every one of the benchmark's 2^20 g g -> t tbar g g points against the oracle."""
+    n = 1 << 20
+    mom = process_points("gg_ttgg", n, 2)
+    got = gpu_me2(me_mod, torch_cuda, "gg_ttgg", mom)
+    rel = check_parity("gg_ttgg", mom, got)
+    print(f"[parity-all] gg_ttgg 2^20: max rel {rel.max():.2e}, p99.9 {np.quantile(rel, 0.999):.2e}, "
+          f"median {np.median(rel):.2e}, beyond 1e-12: {int((rel > TOL).sum())}", flush=True)
 
 
 def test_full_size_ggtt(me_mod, torch_cuda):

@@ -399,3 +399,151 @@ def test_rambo_seeded():
     b = process_points("gg_ttgg", 16, 2)
     c = process_points("gg_ttgg", 16, 3)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# --------------------------------------------------------------------------
+# Route 4: single diagrams (the multi-channel weights)
+# --------------------------------------------------------------------------
+
+def _double_factorial_odd(k):
+    return 1 if k <= 0 else k * _double_factorial_odd(k - 2)
+
+
+@pytest.mark.parametrize("n,total", [(2, 3), (3, 16), (4, 123), (5, 1240)])
+def test_channel_diagram_count(n, total):
+    """Three-point-only diagrams: sum over ordered set partitions of the gluons
+    of the product of (2m - 3)!! (binary trees on m labelled leaves), counted
+    here by set partitions times block orderings; the rest of the process's
+    diagrams (3, 16, 123, 1240) contain a four-gluon vertex."""
+    descs, _ = oracle.channel_diagrams(n)
+    assert len(set(descs)) == len(descs)
+
+    def set_partitions(items):
+        if not items:
+            yield []
+            return
+        first, rest = items[0], items[1:]
+        for part in set_partitions(rest):
+            for i in range(len(part)):
+                yield part[:i] + [[first] + part[i]] + part[i + 1:]
+            yield [[first]] + part
+
+    count = sum(math.factorial(len(p)) * math.prod(_double_factorial_odd(2 * len(b) - 3) for b in p)
+                for p in set_partitions(list(range(n))))
+    assert len(descs) == count
+    assert total - count == {2: 0, 3: 1, 4: 18, 5: 295}[n]
+
+
+def _leaves(tree_desc):
+    return [int(c) for c in tree_desc.replace("(", " ").replace(")", " ").replace(",", " ").split()]
+
+
+def _tree(desc):
+    import ast
+
+    return ast.literal_eval(desc) if "(" in desc else int(desc)
+
+
+def _ordered_coefficient(trees, sigma):
+    """Coefficient of diagram (trees along the top line) in the colour-ordered
+    amplitude of ordering sigma: 0 unless every block and every subtree is
+    contiguous in sigma with the blocks in top-line order; otherwise the product
+    over vertices of +1 (subtree with the smaller label first in sigma) or -1."""
+    pos = {a: i for i, a in enumerate(sigma)}
+    start = 0
+    coef = 1
+
+    def span(t):
+        if isinstance(t, int):
+            return [pos[t]]
+        return span(t[0]) + span(t[1])
+
+    def signs(t):
+        if isinstance(t, int):
+            return 1
+        a, b = span(t[0]), span(t[1])
+        s = 1 if max(a) < min(b) else -1
+        return s * signs(t[0]) * signs(t[1])
+
+    for t in trees:
+        sp = sorted(span(t))
+        if sp != list(range(start, start + len(sp))):
+            return 0
+        # each subtree contiguous
+        def contiguous(u):
+            if isinstance(u, int):
+                return True
+            s = sorted(span(u))
+            return s == list(range(s[0], s[0] + len(s))) and contiguous(u[0]) and contiguous(u[1])
+
+        if not contiguous(t):
+            return 0
+        coef *= signs(t)
+        start += len(sp)
+    return coef
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_single_diagrams_recombine_into_ordered_amplitudes(n, params):
+    """For every gluon ordering sigma and helicity, the colour-ordered amplitude
+    of the recursion with the four-gluon vertex left out equals the sum of the
+    single three-point diagrams consistent with sigma, each with coefficient +-1:
+    the diagram route and the Berends-Giele route agree term by term."""
+    proc = {2: "gg_tt", 3: "gg_ttg", 4: "gg_ttgg"}[n]
+    mom = process_points(proc, 2, 60 + n)[1]
+    perms = oracle.orderings(n)
+    nhel = 1 << (n + 2)
+    rng = np.random.default_rng(n)
+    for h in rng.choice(nhel, 6, replace=False):
+        descs, A = oracle.diagram_amps(n, mom, int(h), params)
+        trees = [[_tree(b) for b in d.split("|")] for d in descs]
+        J3 = oracle.ordered_amps(n, mom, int(h), params, four_gluon=False)
+        for k, sigma in enumerate(perms):
+            c = np.array([_ordered_coefficient(t, sigma) for t in trees], dtype=float)
+            want = J3[k]
+            got = np.dot(c, A)
+            scale = np.abs(A).max()
+            assert abs(got - want) <= 1e-12 * scale, (n, h, sigma, got, want)
+    if n == 2:  # no four-gluon diagrams: the full ordered amplitudes
+        for h in range(nhel):
+            descs, A = oracle.diagram_amps(n, mom, h, params)
+            J = oracle.ordered_amps(n, mom, h, params)
+            trees = [[_tree(b) for b in d.split("|")] for d in descs]
+            for k, sigma in enumerate(perms):
+                c = np.array([_ordered_coefficient(t, sigma) for t in trees], dtype=float)
+                assert abs(np.dot(c, A) - J[k]) <= 1e-12 * np.abs(A).max()
+
+
+def _relabel(desc, perm):
+    """Descriptor of a diagram after gluon relabelling a -> perm[a], in canonical form."""
+    def canon(t):
+        if isinstance(t, int):
+            return perm[t], perm[t]
+        (a, ma), (b, mb) = canon(t[0]), canon(t[1])
+        return ((a, b), min(ma, mb)) if ma < mb else ((b, a), min(ma, mb))
+
+    def fmt(t):
+        return str(t) if isinstance(t, int) else "(" + fmt(t[0]) + "," + fmt(t[1]) + ")"
+
+    return "|".join(fmt(canon(_tree(b))[0]) for b in desc.split("|"))
+
+
+def test_single_diagrams_bose_and_lorentz(params):
+    """Exchanging the two final gluons maps every diagram onto its relabelled
+    partner with the same helicity-summed |A|^2; a rotation of all momenta
+    leaves every diagram's helicity sum unchanged.  (Single diagrams are not
+    boost invariant: the polarisation vectors are transverse in the frame of
+    the momenta, a gauge choice that only the sum of all diagrams forgets.)"""
+    p = zero_width(params)
+    mom = process_points("gg_ttgg", 3, 64)
+    descs, s0 = oracle.diagram_sums("gg_ttgg", mom, p)
+    index = {d: i for i, d in enumerate(descs)}
+    swapped = mom[:, [0, 1, 2, 3, 5, 4]]
+    _, s1 = oracle.diagram_sums("gg_ttgg", swapped, p)
+    perm = [0, 1, 3, 2]
+    for i, d in enumerate(descs):
+        np.testing.assert_allclose(s1[:, index[_relabel(d, perm)]], s0[:, i], rtol=1e-12)
+    rng = np.random.default_rng(9)
+    moved = _boost_rotate(mom, 0.0, rng.normal(size=3), 1.1, rng.normal(size=3))
+    _, s2 = oracle.diagram_sums("gg_ttgg", moved, p)
+    np.testing.assert_allclose(s2, s0, rtol=1e-10)
