@@ -192,6 +192,35 @@ def bench_colour_forms(me, stream, cases):
     return out
 
 
+def bench_multichannel(me, stream, mom, proc, steps):
+    """|M|^2 with the single-diagram weight of each event's channel (channels
+    drawn uniformly, mixed within every wave), against the plain float64 kernel
+    on the same points; a few events checked against the oracle's diagrams."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    m = me.MatrixElement(proc)
+    nchan = len(m.channels())
+    n = mom.shape[0]
+    chan = torch.from_numpy(np.random.default_rng(8).integers(0, nchan, size=n).astype(np.int32)).cuda()
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    alpha = torch.empty(n, dtype=torch.float64, device="cuda")
+    me.me_eval_multichannel(m.ctx, mom, chan, n, out, alpha, stream)
+    k_s, wall = timed(lambda: me.me_eval_multichannel(m.ctx, mom, chan, n, out, alpha, stream), steps, stream)
+    idx = np.arange(0, n, n // 8)
+    descs, sums = oracle.diagram_sums(proc, mom[idx].cpu().numpy())
+    col = {d: i for i, d in enumerate(descs)}
+    gd = m.channels()
+    ch = chan[idx].cpu().numpy()
+    ref = np.array([sums[j, col[gd[c]]] / sums[j].sum() for j, c in enumerate(ch)])
+    dev = float(np.max(np.abs(alpha[idx].cpu().numpy() / ref - 1)))
+    m.close()
+    return {"process": proc, "nevt": n, "channels": nchan, "kernel": f"k_me_gg_mc<proc_{proc}_mc>",
+            "MEs_per_s": n / k_s, "kernel_ms": k_s * 1e3, "max_rel_dev_alpha_vs_oracle": dev, "checked_events": len(idx)}
+
+
 def parity_adjudication(proc, mom_np, got, ref, tol=1e-12):
     """Events beyond tol against the float64 oracle, re-evaluated with the
     __float128 oracle: their deviation from the quad result and the spread of
@@ -327,6 +356,13 @@ def bench_surrogate(me, args, stream):
         log(f"surrogate: epoch {ep + 1}/{args.epochs}")
     torch.cuda.synchronize()
     train_s = time.perf_counter() - tt0
+    # the layered GEMM path of the same step, on a separate network, for comparison
+    net_l = me.Surrogate(seed=1004)
+    net_l.set_fused_step(False)
+    idx_l = perm[:args.batch]
+    net_l.train_step(x, t, idx_l, args.lr, loss, stream)
+    layered_s, _ = timed(lambda: net_l.train_step(x, t, idx_l, args.lr, loss, stream), 100, stream)
+    net_l.close()
     yv = net.forward(x[:n_val])
     val_mse = float(torch.mean((yv - t[:n_val]) ** 2))
     yall = torch.empty(n, dtype=torch.float32, device=dev)
@@ -390,7 +426,9 @@ def bench_surrogate(me, args, stream):
     net.close()
     train_rate = total * args.batch / train_s
     return {
-        "train_samples_per_s": train_rate, "train_epochs": args.epochs,
+        "train_samples_per_s": train_rate, "train_epochs": args.epochs, "train_batch": args.batch,
+        "train_step": "one cooperative kernel per step (forward, backward, batch sums, Adam)",
+        "train_samples_per_s_layered_kernels": args.batch / layered_s,
         "train_tflops": 3 * mlp_flops * train_rate / 1e12,
         "train_frac_of_bf16_mfma_peak": 3 * mlp_flops * train_rate / 1e12 / PEAK["bf16_mfma"],
         "train_points": int(n_fit), "val_mse_standardised_log_me2": val_mse,
@@ -417,12 +455,13 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
     ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,configs,sweep,ps,colour",
+    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,configs,sweep,ps,colour,mc",
                     help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3); "
                          "configs: e+e- -> mu+mu- (16384 points, seed 0) and g g -> t tbar (2^20, seed 1); "
                          "sweep: events per launch 2^10..2^20 at 1, 4, 16, 64 lanes per event; "
                          "ps: the GPU phase-space sampler on the benchmark's workload; "
-                         "colour: float64 kernels with the colour sum on the VALU and on the matrix cores")
+                         "colour: float64 kernels with the colour sum on the VALU and on the matrix cores; "
+                         "mc: the multi-channel form (single-diagram weights)")
     ap.add_argument("--cpu-sample-1t", type=int, default=4096, help="events for the single-thread oracle figure")
     ap.add_argument("--n-train", type=int, default=1 << 22)
     ap.add_argument("--n-calib", type=int, default=1 << 20)
@@ -522,6 +561,10 @@ def main():
     if "colour" in forms:
         line["colour_forms"] = bench_colour_forms(me, stream, [("gg_ttgg", args.nevt, args.seed, 5),
                                                                 ("gg_ttggg", 1 << 18, 3, 2)])
+    if "mc" in forms:
+        line["multichannel"] = bench_multichannel(me, stream, mom if "surrogate" not in forms else
+                                                  torch.from_numpy(mom_np).to(dev), args.process, 5)
+        log(f"multichannel: {line['multichannel']}")
     if "ps" in forms:
         line["phase_space"] = bench_phase_space(me, stream, args.nevt, host_gen_s)
         log(f"phase space: {line['phase_space']['points_per_s']:.3e} points/s")

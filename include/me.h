@@ -102,10 +102,13 @@ int me_eval(me_ctx *ctx, const double *momenta, int64_t nevt, double *out_me2, v
  * ME_FP64 (default): float64 throughout.
  * ME_MIXED: float32 wavefunctions and amplitudes (momentum algebra and
  *   propagator denominators in float64), colour sum as a float16 hi/lo GEMM on
- *   the matrix cores with float32 accumulation, and an a-posteriori estimate of
- *   each event's relative rounding error; every event whose estimate exceeds
- *   rel_tol is recomputed in float64 on the same stream, so each returned
- *   value is expected within rel_tol of the exact float64 result.  Processes
+ *   the matrix cores with float32 accumulation, and a calibrated
+ *   a-posteriori estimate of each event's relative rounding error (not a
+ *   rigorous bound; see me_eval_mixed_diag); every event whose estimate
+ *   exceeds rel_tol is recomputed in float64 on the same stream, so each
+ *   returned value is expected within rel_tol of the exact float64 result
+ *   (measured: all of 2^16 g g -> t tbar g g and 2^12 g g -> t tbar g g g
+ *   events at rel_tol = 1e-5).  Processes
  *   without a mixed form (e+e- -> mu+mu-) keep evaluating in float64.
  *   Mixed evaluation keeps a flagged-event index list in the context; it grows
  *   on the first call with a larger nevt (that call synchronises the device).
@@ -146,7 +149,11 @@ int me_set_colour_form(me_ctx *ctx, int form);
  * me_eval_mixed_diag -- the mixed form without the float64 rerun, for checks
  * (the precision study of the paper's Sec. 3, per event).
  * out_me2:  device float64 [nevt], the float32-form result of every event.
- * out_err:  device float32 [nevt], the estimated relative error.
+ * out_err:  device float32 [nevt], the estimated relative error: a calibrated
+ *           estimate from the magnitudes of the amplitudes added into each
+ *           colour flow, not a rigorous bound (measured against the float64
+ *           oracle it is above the actual error of all but about 3 in 10^5
+ *           g g -> t tbar g g events, by a factor of 25 at the median).
  * out_flag: device uint8 [nevt], 1 where out_err exceeds the context's
  *           tolerance (the events me_eval would recompute in float64).
  * Errors: ME_EINVAL, ME_ESTATE (process without a mixed form), ME_EDEVICE.
@@ -205,6 +212,39 @@ int me_eval_helicities(me_ctx *ctx, const double *momenta, int64_t nevt, double 
  */
 int me_info(const me_ctx *ctx, int *npart, int *ndiag, int *ncol, int *nhel, int *nhel_good,
             double *flops_per_event);
+
+/*
+ * Multi-channel weights (the paper's Sec. 2: the multi-channel integration of
+ * the event generator processes events of different channels in one
+ * matrix-element kernel; a channel is a Feynman diagram, and the event's
+ * weight in its channel is that diagram's share of the sum over diagrams of
+ * |A_d|^2, the single-diagram enhancement).
+ *
+ * me_channels -- *nchan receives the number of channels of the context's
+ *   process: its Feynman diagrams whose gluons meet at three-point vertices
+ *   only (diagrams with a four-gluon vertex are not channels); 0 when the
+ *   process has no multi-channel form ("gg_tt", "gg_ttg", "gg_ttgg" have one).
+ * me_channel_desc -- the descriptor of channel `chan` into buf (NUL-terminated,
+ *   buflen bytes): the gluon trees of the diagram in order along the top line
+ *   from ubar(p3) to v(p4), separated by '|', each tree written as nested
+ *   "(x,y)" with the subtree holding the smaller gluon label first; gluon
+ *   labels 0, 1 are the incoming gluons, 2, 3, ... the final ones in particle
+ *   order.  Channels are numbered in the lexicographic order of descriptors.
+ *   Errors: ME_EINVAL (chan out of range, buffer too short), ME_ESTATE.
+ * me_eval_multichannel -- for nevt points and a channel per point:
+ *   momenta: device float64 [nevt][npart][4]; chan: device int32 [nevt];
+ *   out_me2: device float64 [nevt], |M|^2 as from me_eval;
+ *   out_alpha: device float64 [nevt], sum over helicities of |A_chan|^2
+ *   divided by the same sum over all channel diagrams (colour factors
+ *   stripped so that every colour-flow coefficient has unit modulus); 0 when
+ *   chan is outside 0 .. nchan - 1.  The evaluation is float64 with one
+ *   amplitude per Feynman diagram (no merged currents).  Errors: ME_EINVAL,
+ *   ME_ESTATE (no multi-channel form), ME_EDEVICE.
+ */
+int me_channels(const me_ctx *ctx, int *nchan);
+int me_channel_desc(const me_ctx *ctx, int chan, char *buf, int buflen);
+int me_eval_multichannel(me_ctx *ctx, const double *momenta, const int32_t *chan, int64_t nevt, double *out_me2,
+                         double *out_alpha, void *stream);
 
 /*
  * me_flops -- the floating-point operation counts behind me_info's total, per

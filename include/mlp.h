@@ -86,6 +86,18 @@ int mlp_train_step(me_mlp *mlp, const float *x, const float *t, const int32_t *i
 int mlp_backward(me_mlp *mlp, const float *x, const float *t, const int32_t *idx, int64_t n, float *grad_dev,
                  float *loss_dev, void *stream);
 
+/*
+ * mlp_set_fused_step -- choose how mlp_train_step and mlp_backward run.
+ * on != 0 (default where it applies): one cooperative kernel per step (width
+ * 256, depth <= 4, n_in <= 32, batch a multiple of 128): rows go through the
+ * whole forward and backward chain without leaving the block, and the batch
+ * sums of the weight gradients and the Adam update follow after grid-wide
+ * barriers.  on == 0: the layered GEMM kernels.  Both give the same gradients
+ * up to the order of the FP32 sums.  Errors: ME_ESTATE (shape not supported
+ * by the fused kernel).
+ */
+int mlp_set_fused_step(me_mlp *mlp, int on);
+
 int mlp_free(me_mlp *mlp);
 
 /*

@@ -51,6 +51,9 @@ def lib():
     L.me_info.argtypes = [vp, ip, ip, ip, ip, ip, dp]
     L.me_good_helicities.argtypes = [vp, ip, ip]
     L.me_flops.argtypes = [vp, dp, dp, dp]
+    L.me_channels.argtypes = [vp, ip]
+    L.me_channel_desc.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+    L.me_eval_multichannel.argtypes = [vp, vp, vp, i64, vp, vp, vp]
     L.me_set_precision.argtypes = [vp, ctypes.c_int, ctypes.c_double]
     L.me_set_helicity_lanes.argtypes = [vp, ctypes.c_int]
     L.me_set_colour_form.argtypes = [vp, ctypes.c_int]
@@ -179,6 +182,30 @@ def me_good_helicities(ctx) -> list:
     return list(buf[:cnt.value])
 
 
+def me_channels(ctx) -> list:
+    """Descriptors of the process's channels (empty without a multi-channel form)."""
+    n = ctypes.c_int()
+    _check(lib().me_channels(ctx, ctypes.byref(n)), "me_channels")
+    out = []
+    buf = ctypes.create_string_buffer(256)
+    for i in range(n.value):
+        _check(lib().me_channel_desc(ctx, i, buf, 256), "me_channel_desc")
+        out.append(buf.value.decode())
+    return out
+
+
+def me_eval_multichannel(ctx, momenta, chan, nevt: int, out_me2, out_alpha, stream=None) -> None:
+    nevt = _nevt(nevt)
+    npart, _ = _ctx_sizes(ctx)
+    _need(momenta, nevt * npart * 4, "momenta")
+    for t, what in ((chan, "chan"), (out_me2, "out_me2"), (out_alpha, "out_alpha")):
+        _need(t, nevt, what)
+    _check(lib().me_eval_multichannel(ctx, _dev_ptr(momenta, "float64", "momenta"), _dev_ptr(chan, "int32", "chan"),
+                                      nevt, _dev_ptr(out_me2, "float64", "out_me2"),
+                                      _dev_ptr(out_alpha, "float64", "out_alpha"), _stream_handle(stream)),
+           "me_eval_multichannel")
+
+
 def me_set_precision(ctx, mode: int, rel_tol: float = 1e-5) -> None:
     _check(lib().me_set_precision(ctx, int(mode), float(rel_tol)), "me_set_precision")
 
@@ -279,6 +306,20 @@ class MatrixElement:
     def set_colour_form(self, form):
         me_set_colour_form(self.ctx, form)
 
+    def channels(self) -> list:
+        return me_channels(self.ctx)
+
+    def eval_multichannel(self, momenta, chan, stream=None):
+        """(|M|^2, single-diagram weight of each event's channel)."""
+        import torch
+
+        self._check_mom(momenta)
+        n = momenta.shape[0]
+        out = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        alpha = torch.empty(n, dtype=torch.float64, device=momenta.device)
+        me_eval_multichannel(self.ctx, momenta, chan, n, out, alpha, stream)
+        return out, alpha
+
     def eval_mixed_diag(self, momenta, stream=None):
         """Mixed form without the float64 rerun: (me2, error estimate, flag)."""
         import torch
@@ -361,6 +402,7 @@ def _mlp_sigs(L):
     L.mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, vp]
     L.mlp_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     L.mlp_free.argtypes = [vp]
+    L.mlp_set_fused_step.argtypes = [vp, ctypes.c_int]
     L.me_features.argtypes = [vp, i64, ctypes.c_int, vp, vp]
     L.unweight_two_stage.argtypes = [vp, vp, vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, vp, vp, vp, vp]
@@ -441,6 +483,10 @@ def mlp_backward(h, x, t, idx, n, grad, loss=None, stream=None) -> None:
                                          _opt_ptr(loss, "float32", "loss"), _stream_handle(stream)), "mlp_backward")
 
 
+def mlp_set_fused_step(h, on: bool) -> None:
+    _check(_mlp_sigs(lib()).mlp_set_fused_step(h, int(bool(on))), "mlp_set_fused_step")
+
+
 def mlp_free(h) -> None:
     _check(_mlp_sigs(lib()).mlp_free(h), "mlp_free")
 
@@ -497,6 +543,9 @@ class Surrogate:
     def train_step(self, x, t, idx, lr, loss=None, stream=None):
         n = idx.shape[0] if idx is not None else x.shape[0]
         mlp_train_step(self.h, x, t, idx, n, lr, loss, stream)
+
+    def set_fused_step(self, on):
+        mlp_set_fused_step(self.h, on)
 
     def backward(self, x, t, idx=None, stream=None):
         import torch

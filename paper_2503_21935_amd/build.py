@@ -65,7 +65,35 @@ static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, c
 extern const me_process_desc me_desc_{name} = {{
     "{name}", {kind}, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
     {proc}::flops_amp, {proc}::flops_colour, {proc}::flops_executed, launch_f64, launch_f64_idx, {mixed_ptr}, {cest},
-    {colerr}, {cm_ptr}}};
+    {colerr}, {cm_ptr}, {mc_ptr}, {mc_n}, {mc_desc}}};
+#endif
+"""
+
+_MC_DECL = """
+#ifndef __HIP_DEVICE_COMPILE__
+// the multi-channel kernel is compiled in a translation unit of its own
+hipError_t me_launch_mc_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                               const me_params& prm, const int* chan, double* alpha, hipStream_t s);
+extern const int me_nchan_{name};
+extern const char* const* const me_chan_desc_{name};
+#endif
+"""
+
+_TU_MC = """// Generated translation unit: multi-channel kernel of {name}.
+#include "me_kernels.h"
+#include "gen/proc_{name}_mc.h"
+
+hipError_t me_launch_mc_{name}(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                               const me_params& prm, const int* chan, double* alpha, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL((k_me_gg_mc<proc_{name}_mc>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
+                       chan, alpha);
+    return hipGetLastError();
+}}
+
+#ifndef __HIP_DEVICE_COMPILE__
+extern const int me_nchan_{name} = proc_{name}_mc::nchan;
+extern const char* const* const me_chan_desc_{name} = channel_desc_{name};
 #endif
 """
 
@@ -110,7 +138,7 @@ hipError_t me_launch_f64_cm_{name}(const double* mom, int64_t nevt, double* out,
 extern const me_process_desc me_desc_{name} = {{
     "{name}", ME_KIND_GG, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
     {proc}::flops_amp, {proc}::flops_colour, {proc}::flops_executed, launch_f64, launch_f64_idx, me_launch_mixed_{name}, {cest},
-    {proc}::colour_err_f16, me_launch_f64_cm_{name}}};
+    {proc}::colour_err_f16, me_launch_f64_cm_{name}, nullptr, 0, nullptr}};
 #endif
 """
 
@@ -177,7 +205,7 @@ def _write(path, text):
 
 def generate_sources(processes):
     sys.path.insert(0, os.path.dirname(HERE))
-    from paper_2503_21935_amd.gen import generate
+    from paper_2503_21935_amd.gen import MULTICHANNEL, generate
 
     info = generate(GEN, [p for p in processes if p.startswith("gg_")])
     tus = []
@@ -202,9 +230,16 @@ def generate_sources(processes):
         cm, cm_ptr = ("", "nullptr")
         if name in CM:
             cm, cm_ptr = _CM.format(proc=proc), "launch_f64_cm"
+        mc_ptr, mc_n, mc_desc = "nullptr", "0", "nullptr"
+        if name in MULTICHANNEL:
+            cm += _MC_DECL.format(name=name)
+            mc_ptr, mc_n, mc_desc = f"me_launch_mc_{name}", f"me_nchan_{name}", f"me_chan_desc_{name}"
+            path_mc = os.path.join(GEN, f"tu_{name}_mc.hip")
+            _write(path_mc, _TU_MC.format(name=name))
+            tus.append(path_mc)
         _write(path, _TU.format(name=name, include=inc, kernel=kernel, proc=proc, kind=kind, mixed=mixed,
                                 mixed_ptr=mixed_ptr, cest=MIXED_CEST.get(name, 8.0), colerr=colerr, cm=cm,
-                                cm_ptr=cm_ptr))
+                                cm_ptr=cm_ptr, mc_ptr=mc_ptr, mc_n=mc_n, mc_desc=mc_desc))
         tus.append(path)
     decls = "\n".join(f"extern const me_process_desc me_desc_{n};" for n in processes)
     ptrs = ", ".join(f"&me_desc_{n}" for n in processes)

@@ -368,6 +368,35 @@ int me_info(const me_ctx* c, int* npart, int* ndiag, int* ncol, int* nhel, int* 
     return ME_OK;
 }
 
+int me_channels(const me_ctx* c, int* nchan) {
+    if (!c || !nchan) return fail(ME_EINVAL, "null argument");
+    *nchan = c->proc->launch_mc ? c->proc->nchan : 0;
+    return ME_OK;
+}
+
+int me_channel_desc(const me_ctx* c, int chan, char* buf, int buflen) {
+    if (!c || !buf || buflen < 1) return fail(ME_EINVAL, "null argument");
+    if (!c->proc->launch_mc) return fail(ME_ESTATE, std::string("no multi-channel form for ") + c->proc->name);
+    if (chan < 0 || chan >= c->proc->nchan) return fail(ME_EINVAL, "channel out of range");
+    const char* d = c->proc->chan_desc[chan];
+    const size_t len = std::strlen(d);
+    if ((int)len >= buflen) return fail(ME_EINVAL, "buffer too short");
+    std::memcpy(buf, d, len + 1);
+    return ME_OK;
+}
+
+int me_eval_multichannel(me_ctx* c, const double* momenta, const int32_t* chan, int64_t nevt, double* out_me2,
+                         double* out_alpha, void* stream) {
+    if (!c || nevt < 0) return fail(ME_EINVAL, "null context or negative nevt");
+    if (!c->proc->launch_mc) return fail(ME_ESTATE, std::string("no multi-channel form for ") + c->proc->name);
+    if (nevt == 0) return ME_OK;
+    if (!momenta || !chan || !out_me2 || !out_alpha) return fail(ME_EINVAL, "null buffer");
+    if (nevt > 0x7fffffffLL) return fail(ME_EINVAL, "nevt above 2^31 - 1");
+    HIP_CHECK(c->proc->launch_mc(momenta, nevt, out_me2, c->d_good, c->nhel_good, c->prm, chan, out_alpha,
+                                 (hipStream_t)stream));
+    return ME_OK;
+}
+
 int me_flops(const me_ctx* c, double* amp_per_hel, double* colour_per_hel, double* executed_per_hel) {
     if (!c) return fail(ME_EINVAL, "null context");
     if (amp_per_hel) *amp_per_hel = c->proc->flops_amp;

@@ -203,6 +203,43 @@ __global__ __launch_bounds__(ME_BLOCK) void k_me_gg_cm(const double* __restrict_
     if (valid && grp == 0) out[ev] = tot * (1.0 / (256.0 * P::identical * P::lcd));
 }
 
+// Multi-channel form: the program of P (the unmerged plan: one amplitude per
+// Feynman diagram) also sums, over the helicities, |A_d|^2 over the channel
+// diagrams d (those with three-point vertices only) and |A_c|^2 for the
+// event's channel c = chan[ev]; alpha[ev] = sum_h |A_c|^2 / sum_h sum_d |A_d|^2
+// is the single-diagram-enhancement weight of the paper's multi-channel
+// integration (Sec. 2: events of different channels in one kernel), 0 for a
+// channel id outside 0 .. P::nchan - 1.  out[ev] is |M|^2 as from k_me_gg.
+// The channel only selects which |A_d|^2 enters the numerator (a select, no
+// branch), so events of different channels share a wave at no cost.
+template <class P>
+__global__ __launch_bounds__(ME_BLOCK) void k_me_gg_mc(const double* __restrict__ mom, int64_t nevt,
+                                                       double* __restrict__ out, const int* __restrict__ hels,
+                                                       int nh, me_params prm, const int* __restrict__ chan,
+                                                       double* __restrict__ alpha) {
+    const int64_t ev = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ev >= nevt) return;
+    using T = double;
+    constexpr int NG = P::ngluon;
+    static_assert(ME_BLOCK == 64, "one wave per block");
+    __shared__ double Qt[ME_MOM_ROW(NG + 2)];
+    gg_ext<T, NG> x;
+    gg_setup<P, T>(x, mom, ev, Qt, threadIdx.x, prm);
+    const int ch = chan[ev];
+    T acc = T(0), num = T(0), den = T(0);
+#pragma unroll 1
+    for (int ih = 0; ih < nh; ++ih) {
+        gg_externals<P, T>(x, hels[ih]);
+        cx<T> J[P::ncol];
+#pragma unroll
+        for (int k = 0; k < P::ncol; ++k) J[k] = mk(T(0), T(0));
+        P::template amps<T>(x, J, ch, num, den);
+        acc += P::template colour_sum<T>(J);
+    }
+    out[ev] = double(acc) * (1.0 / (256.0 * P::identical * P::lcd));
+    alpha[ev] = num / den;
+}
+
 template <class P>
 __global__ __launch_bounds__(ME_BLOCK) void k_me_ee(const double* __restrict__ mom, int64_t nevt,
                                                     double* __restrict__ out, const int* __restrict__ hels,

@@ -24,6 +24,10 @@ typedef hipError_t (*me_launch_mixed_fn)(const double* mom, int64_t nevt, double
                                          int* flag_idx, float* err_out, unsigned char* flag_out,
                                          hipStream_t stream);
 
+// Multi-channel form: |M|^2 and the single-diagram weight of each event's channel.
+typedef hipError_t (*me_launch_mc_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                      const me_params& prm, const int* chan, double* alpha, hipStream_t stream);
+
 enum { ME_KIND_EE = 0, ME_KIND_GG = 1 };
 
 struct me_process_desc {
@@ -38,6 +42,9 @@ struct me_process_desc {
     double mixed_cest;                // calibration of the amplitude error estimate
     double colour_err;                // a-priori error of the float16 hi/lo colour sum
     me_launch_fn launch_f64_cm;       // float64 with the colour sum on the matrix cores (nullptr: none)
+    me_launch_mc_fn launch_mc;        // multi-channel form (nullptr: none)
+    int nchan;                        // its channels
+    const char* const* chan_desc;     // their descriptors
 };
 
 const me_process_desc* me_find_process(const char* name);

@@ -1,6 +1,7 @@
 // mlp.hip -- surrogate network kernels: BF16 matrix-core GEMMs with FP32
 // accumulation and fused epilogues, loss, reductions, Adam; the C ABI of
 // include/mlp.h.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -340,7 +341,7 @@ struct layer_map {
 // of the weight matrices (first layer padded to 32 inputs).
 __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int64_t np, float lr, float c1, float c2, layer_map L,
-                       int depth, int width, bf16* const* __restrict__ wbf) {
+                       int depth, int width, bf16* const* __restrict__ wbf, bf16* const* __restrict__ wbft) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     const float gi = g[i];
@@ -357,6 +358,7 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
             const int64_t r = (i - o) / fi, k = (i - o) % fi;
             const int ld = (l == 0) ? MLP_KPAD : fi;
             wbf[l][r * ld + k] = (bf16)th;
+            if (l > 0) wbft[l][k * width + r] = (bf16)th;
         }
     }
 }
@@ -367,6 +369,316 @@ __global__ void k_to_bf16(const float* __restrict__ theta, int64_t o, int rows, 
     if (i >= (int64_t)rows * ld) return;
     const int64_t r = i / ld, k = i % ld;
     w[i] = (bf16)(k < fi ? theta[o + r * fi + k] : 0.f);
+}
+
+// transposed BF16 copy wt[k][r] = theta[o + r fi + k] of a hidden weight matrix
+__global__ void k_to_bf16_t(const float* __restrict__ theta, int64_t o, int rows, int fi, bf16* __restrict__ wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * fi) return;
+    const int64_t k = i / rows, r = i % rows;
+    wt[i] = (bf16)theta[o + r * fi + k];
+}
+
+// ---------------------------------------------------------------------------
+// Fused training step for width 256 (one cooperative launch, two grid-wide
+// barriers).  The batch's rows are independent through the whole forward and
+// backward chain, so phase 1 gives each block tiles of FT_R rows and carries
+// them through every layer forward (activations and pre-activations in LDS),
+// the output layer and loss, and every layer backward down to the first
+// pre-activation gradient, reading the BF16 weights (and their transposes)
+// from L2.  The only cross-row work is the weight and bias gradients, sums
+// over the batch: after the first barrier, phase 2 computes them as GEMMs
+// dW_l = dZ_l^T H_{l-1} on 64 x 64 output tiles, each over a quarter of the
+// batch (partial slabs in a fixed layout), from the transposed activation and
+// gradient copies phase 1 left in global memory (16-byte MFMA fragments).
+// After the second barrier, phase 3 adds the slabs in a fixed order (the
+// result does not depend on the grid) and applies Adam to the FP32 masters,
+// refreshing the BF16 copies.  Rounding points are those of the layered path.
+// ---------------------------------------------------------------------------
+#define FT_R 16        // rows per phase-1 tile
+#define FT_S 4         // batch splits of the weight gradients
+#define FT_MAXDEPTH 4  // pre-activations of every layer stay in LDS
+
+struct ft_args {
+    const float* x;           // [*][n_in]
+    const float* t;           // targets
+    const int32_t* idx;       // batch rows (nullptr: the first M)
+    int64_t M;                // batch size (multiple of FT_S * 32)
+    int n_in, depth;
+    const bf16* w[FT_MAXDEPTH];   // [256][ld] (ld 32 for the first layer)
+    const bf16* wt[FT_MAXDEPTH];  // transposed copies [fan_in][256] (layers >= 1)
+    bf16* wbf[FT_MAXDEPTH];       // BF16 copies to refresh after the update
+    bf16* wbft[FT_MAXDEPTH];
+    float* theta;             // FP32 masters (flat layout)
+    float *m, *v;             // Adam moments
+    float* grad_out;          // gradient only (no update) when non-null
+    layer_map L;
+    int64_t wout_off, bout_off, np;
+    bf16* XT;                 // [32][M]
+    bf16* HT[FT_MAXDEPTH];    // [256][M]
+    bf16* DZT[FT_MAXDEPTH];   // [256][M]
+    float* dy;                // [M]
+    float* slab;              // [FT_S][np]
+    float* lossp;             // [gridDim.x]
+    float* loss;              // [1] or nullptr
+    float lr, c1, c2;
+};
+
+__device__ __forceinline__ float silu_d(float z) {
+    const float s = sigmoidf_(z);
+    return s * (1.f + z * (1.f - s));
+}
+
+__global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
+    namespace cg = cooperative_groups;
+    cg::grid_group grid = cg::this_grid();
+    constexpr int W = MLPF_W, P = MLPF_PITCH;
+    __shared__ __attribute__((aligned(16))) bf16 Hs[FT_R * P];   // layer input / output
+    __shared__ __attribute__((aligned(16))) bf16 Gs[FT_R * P];   // pre-activation gradient
+    __shared__ float Zs[FT_MAXDEPTH][FT_R][W];                  // pre-activations
+    __shared__ float dys[FT_R];
+    __shared__ float red[256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t M = a.M;
+    const int nrt = (int)(M / FT_R);
+    float loss_acc = 0.f;
+
+    // ---------------- phase 1: rows through forward and backward ----------------
+    for (int rt = blockIdx.x; rt < nrt; rt += gridDim.x) {
+        const int64_t m0 = (int64_t)rt * FT_R;
+        for (int e = tid; e < FT_R * MLP_KPAD; e += 256) {
+            const int r = e / MLP_KPAD, k = e % MLP_KPAD;
+            const int64_t src = a.idx ? a.idx[m0 + r] : m0 + r;
+            const bf16 v = (bf16)(k < a.n_in ? a.x[src * a.n_in + k] : 0.f);
+            Hs[r * P + k] = v;
+            a.XT[(int64_t)k * M + m0 + r] = v;
+        }
+        __syncthreads();
+        int K = MLP_KPAD;
+        for (int l = 0; l < a.depth; ++l) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const bf16* Wl = a.w[l];
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Hs + li * P + k0 + 8 * lg);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * wave + 16 * t + li) * K + k0 + 8 * lg);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // the layer input has been read by every wave
+            const float* bias = a.theta + a.L.b_off[l];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = 64 * wave + 16 * t + li;
+                const float bc = bias[c];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 4 * lg + v;
+                    const float z = acc[t][v] + bc;
+                    Zs[l][r][c] = z;
+                    const bf16 h = (bf16)(z * sigmoidf_(z));
+                    Hs[r * P + c] = h;
+                    a.HT[l][(int64_t)c * M + m0 + r] = h;
+                }
+            }
+            __syncthreads();
+            K = W;
+        }
+        // output layer, residual, loss, dy (16 threads per row)
+        {
+            const int r = tid >> 4, part = tid & 15;
+            const bf16x8* hr = reinterpret_cast<const bf16x8*>(Hs + r * P + part * 16);
+            const float* wo = a.theta + a.wout_off + part * 16;
+            float s = 0.f;
+#pragma unroll
+            for (int k8 = 0; k8 < 2; ++k8) {
+                const bf16x8 hv = hr[k8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s = fmaf((float)hv[q], wo[8 * k8 + q], s);
+            }
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
+            if (part == 0) {
+                const int64_t m = m0 + r;
+                const float y = s + a.theta[a.bout_off];
+                const float res = y - a.t[a.idx ? a.idx[m] : m];
+                const float d = 2.f * res / (float)M;
+                dys[r] = d;
+                a.dy[m] = d;
+                loss_acc += res * res;
+            }
+        }
+        __syncthreads();
+        // dZ of the last hidden layer
+        {
+            const int l = a.depth - 1;
+            const float* wo = a.theta + a.wout_off;
+            for (int e = tid; e < FT_R * W; e += 256) {
+                const int r = e / W, c = e % W;
+                const bf16 g = (bf16)(dys[r] * wo[c] * silu_d(Zs[l][r][c]));
+                Gs[r * P + c] = g;
+                a.DZT[l][(int64_t)c * M + m0 + r] = g;
+            }
+        }
+        __syncthreads();
+        // backward through the hidden layers: dZ_{l-1} = (dZ_l W_l) silu'(Z_{l-1})
+        for (int l = a.depth - 1; l >= 1; --l) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const bf16* WT = a.wt[l];  // [k][n]
+            for (int n0 = 0; n0 < W; n0 += 32) {
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Gs + li * P + n0 + 8 * lg);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(WT + (int64_t)(64 * wave + 16 * t + li) * W + n0 + 8 * lg);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // Gs has been read by every wave
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int k = 64 * wave + 16 * t + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 4 * lg + v;
+                    const bf16 g = (bf16)(acc[t][v] * silu_d(Zs[l - 1][r][k]));
+                    Gs[r * P + k] = g;
+                    a.DZT[l - 1][(int64_t)k * M + m0 + r] = g;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    red[tid] = loss_acc;
+    __syncthreads();
+    if (tid == 0) {
+        float s = 0.f;
+        for (int i = 0; i < 256; ++i) s += red[i];
+        a.lossp[blockIdx.x] = s;
+    }
+    __threadfence();
+    grid.sync();
+
+    // ---------------- phase 2: batch sums (weight and bias gradients) ----------------
+    if (blockIdx.x == 0 && a.loss) {
+        if (tid == 0) {
+            float s = 0.f;
+            for (int i = 0; i < (int)gridDim.x; ++i) s += a.lossp[i];
+            a.loss[0] = s / (float)M;
+        }
+    }
+    const int64_t span = M / FT_S;
+    // items: for each split s: per layer l, 4 n-blocks x nkb(l) k-blocks of 64, then one output-layer item
+    int per_split = 1;
+    for (int l = 0; l < a.depth; ++l) per_split += 4 * ((a.L.fan_in[l] + 63) / 64);
+    const int nitems = per_split * FT_S;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int s = it / per_split;
+        int j = it % per_split;
+        const int64_t mb = (int64_t)s * span;
+        float* slab = a.slab + (int64_t)s * a.np;
+        if (j == per_split - 1) {
+            // output layer: dw_out[k] = sum_m dy[m] H_last[m][k], db_out = sum_m dy[m]
+            const bf16* HT = a.HT[a.depth - 1];
+            const int k = tid;
+            float acc = 0.f;
+            for (int64_t m = mb; m < mb + span; m += 8) {
+                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(HT + (int64_t)k * M + m);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) acc = fmaf(a.dy[m + q], (float)hv[q], acc);
+            }
+            slab[a.wout_off + k] = acc;
+            if (tid == 0) {
+                float d = 0.f;
+                for (int64_t m = mb; m < mb + span; ++m) d += a.dy[m];
+                slab[a.bout_off] = d;
+            }
+            continue;
+        }
+        int l = 0;
+        for (; l < a.depth; ++l) {
+            const int nl = 4 * ((a.L.fan_in[l] + 63) / 64);
+            if (j < nl) break;
+            j -= nl;
+        }
+        const int nkb = (a.L.fan_in[l] + 63) / 64;
+        const int nb = j / nkb, kb = j % nkb;
+        const int fi = a.L.fan_in[l];
+        const int kw = (l == 0) ? MLP_KPAD : W;  // rows of the transposed input copy
+        const bf16* A = a.DZT[l];                // [n][m]
+        const bf16* B = (l == 0) ? a.XT : a.HT[l - 1];  // [k][m]
+        const int n0 = 64 * nb + 16 * wave;
+        const int ntile = min(4, (min(kw, 64 * kb + 64) - 64 * kb) / 16);
+        f32x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        float bsum = 0.f;
+        for (int64_t m = mb; m < mb + span; m += 32) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (int64_t)(n0 + li) * M + m + 8 * lg);
+            if (kb == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) bsum += (float)av[q];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < ntile) {
+                    const int k = 64 * kb + 16 * t + li;
+                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(B + (int64_t)k * M + m + 8 * lg);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t >= ntile) continue;
+            const int k = 64 * kb + 16 * t + li;
+            if (k >= fi) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = n0 + 4 * lg + v;
+                slab[a.L.w_off[l] + (int64_t)n * fi + k] = acc[t][v];
+            }
+        }
+        if (kb == 0) {
+            bsum += __shfl_xor(bsum, 16);
+            bsum += __shfl_xor(bsum, 32);
+            if (lg == 0) slab[a.L.b_off[l] + n0 + li] = bsum;
+        }
+    }
+    __threadfence();
+    grid.sync();
+
+    // ---------------- phase 3: sum the slabs, Adam, BF16 copies ----------------
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < a.np; i += (int64_t)gridDim.x * 256) {
+        float g = 0.f;
+#pragma unroll
+        for (int s = 0; s < FT_S; ++s) g += a.slab[(int64_t)s * a.np + i];
+        if (a.grad_out) {
+            a.grad_out[i] = g;
+            continue;
+        }
+        const float mi = 0.9f * a.m[i] + 0.1f * g;
+        const float vi = 0.999f * a.v[i] + 0.001f * g * g;
+        a.m[i] = mi;
+        a.v[i] = vi;
+        const float th = a.theta[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + 1e-8f);
+        a.theta[i] = th;
+        for (int l = 0; l < a.depth; ++l) {
+            const int64_t o = a.L.w_off[l];
+            const int fi = a.L.fan_in[l];
+            if (i >= o && i < o + (int64_t)W * fi) {
+                const int64_t r = (i - o) / fi, k = (i - o) % fi;
+                const int ld = (l == 0) ? MLP_KPAD : fi;
+                a.wbf[l][r * ld + k] = (bf16)th;
+                if (l > 0) a.wbft[l][k * W + r] = (bf16)th;
+            }
+        }
+    }
 }
 
 __global__ void k_features(const double* __restrict__ mom, int64_t n, int npart, float* __restrict__ x) {
@@ -391,6 +703,13 @@ struct me_mlp {
     float* dwpart;           // split-K partial slabs of one weight gradient [MLP_DW_SPLITS][width][fan_in]
     std::vector<bf16*> wbf;  // per hidden layer, [width][ld]
     bf16** d_wbf;            // device array of those pointers
+    std::vector<bf16*> wbft; // transposed copies [fan_in][width] (layers >= 1; the backward pass)
+    bf16** d_wbft;
+    bool fused;              // training step as one cooperative kernel where it applies
+    int fgrid;               // its grid: co-resident blocks
+    int64_t fcap;            // batch capacity of its buffers
+    bf16 *XT, *HTb, *DZTb;   // transposed input, activations and gradients [feature][batch]
+    float *fslab, *flossp, *fdy;
     int64_t cap;             // activation capacity (rows)
     bf16* X;
     std::vector<bf16*> H;
@@ -459,6 +778,11 @@ static hipError_t refresh_bf16(me_mlp* p, hipStream_t s) {
         const int64_t tot = (int64_t)p->width * ld;
         hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p->theta, p->L.w_off[l],
                            p->width, fi, ld, p->wbf[l]);
+        if (l > 0) {
+            const int64_t nt = (int64_t)p->width * fi;
+            hipLaunchKernelGGL(k_to_bf16_t, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p->theta,
+                               p->L.w_off[l], p->width, fi, p->wbft[l]);
+        }
     }
     return hipGetLastError();
 }
@@ -593,6 +917,7 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
     p->H.assign(depth, nullptr);
     p->Z.assign(depth, nullptr);
     p->wbf.assign(depth, nullptr);
+    p->wbft.assign(depth, nullptr);
     std::vector<float> h(o, 0.f);
     uint64_t st = seed;
     for (int l = 0; l < depth; ++l) {
@@ -620,9 +945,23 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
         const int ld = (l == 0) ? MLP_KPAD : p->L.fan_in[l];
         if (bad(hipMalloc(&p->wbf[l], (size_t)width * ld * sizeof(bf16))))
             return me_fail(ME_ENOMEM, "mlp_create: device allocation");
+        if (l > 0 && bad(hipMalloc(&p->wbft[l], (size_t)width * p->L.fan_in[l] * sizeof(bf16))))
+            return me_fail(ME_ENOMEM, "mlp_create: device allocation");
+    }
+    p->fused = (width == MLPF_W && depth <= FT_MAXDEPTH && n_in <= MLP_KPAD);
+    p->fgrid = 0;
+    if (p->fused) {
+        int dev = 0, cus = 0, per = 0;
+        if (bad(hipGetDevice(&dev)) || bad(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) ||
+            bad(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mlp_train_fused, 256, 0)))
+            return me_fail(ME_EDEVICE, "mlp_create: occupancy query");
+        p->fgrid = cus * per;
+        if (p->fgrid < 1) p->fused = false;
     }
     if (bad(hipMalloc(&p->d_wbf, depth * sizeof(bf16*))) ||
         bad(hipMemcpy(p->d_wbf, p->wbf.data(), depth * sizeof(bf16*), hipMemcpyHostToDevice)) ||
+        bad(hipMalloc(&p->d_wbft, depth * sizeof(bf16*))) ||
+        bad(hipMemcpy(p->d_wbft, p->wbft.data(), depth * sizeof(bf16*), hipMemcpyHostToDevice)) ||
         bad(hipMemcpy(p->theta, h.data(), o * sizeof(float), hipMemcpyHostToDevice)) ||
         bad(hipMemset(p->m, 0, o * sizeof(float))) || bad(hipMemset(p->v, 0, o * sizeof(float))) ||
         bad(hipMemset(p->grad, 0, o * sizeof(float))) || bad(refresh_bf16(p, nullptr)) ||
@@ -696,6 +1035,85 @@ int mlp_forward(me_mlp* p, const float* x, int64_t n, float* y, void* stream) {
     return ME_OK;
 }
 
+// Batch buffers of the fused step (grow on the first call with a larger batch;
+// that call synchronises the device).
+static int ensure_fused(me_mlp* p, int64_t M) {
+    if (M <= p->fcap) return ME_OK;
+    HCHK(hipDeviceSynchronize());
+    auto f = [](void* q) {
+        if (q) (void)hipFree(q);
+    };
+    f(p->XT);
+    f(p->HTb);
+    f(p->DZTb);
+    f(p->fslab);
+    f(p->flossp);
+    f(p->fdy);
+    p->XT = p->HTb = p->DZTb = nullptr;
+    p->fslab = p->flossp = p->fdy = nullptr;
+    p->fcap = 0;
+    const int64_t W = p->width;
+    HCHK(hipMalloc(&p->XT, MLP_KPAD * M * sizeof(bf16)));
+    HCHK(hipMalloc(&p->HTb, p->depth * W * M * sizeof(bf16)));
+    HCHK(hipMalloc(&p->DZTb, p->depth * W * M * sizeof(bf16)));
+    HCHK(hipMalloc(&p->fslab, FT_S * p->np * sizeof(float)));
+    HCHK(hipMalloc(&p->flossp, p->fgrid * sizeof(float)));
+    HCHK(hipMalloc(&p->fdy, M * sizeof(float)));
+    p->fcap = M;
+    return ME_OK;
+}
+
+static bool fused_applies(const me_mlp* p, int64_t n) {
+    return p->fused && n >= FT_S * 32 && n % (FT_S * 32) == 0 && n <= (int64_t)1 << 24;
+}
+
+// One training step (grad_out == nullptr) or the gradient only, as the fused
+// cooperative kernel.
+static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float lr,
+                      float* loss, float* grad_out, hipStream_t s) {
+    int rc = ensure_fused(p, n);
+    if (rc != ME_OK) return rc;
+    ft_args a{};
+    a.x = x;
+    a.t = t;
+    a.idx = idx;
+    a.M = n;
+    a.n_in = p->n_in;
+    a.depth = p->depth;
+    for (int l = 0; l < p->depth; ++l) {
+        a.w[l] = p->wbf[l];
+        a.wt[l] = p->wbft[l];
+        a.wbf[l] = p->wbf[l];
+        a.wbft[l] = p->wbft[l];
+        a.HT[l] = p->HTb + (int64_t)l * p->width * n;
+        a.DZT[l] = p->DZTb + (int64_t)l * p->width * n;
+    }
+    a.theta = p->theta;
+    a.m = p->m;
+    a.v = p->v;
+    a.grad_out = grad_out;
+    a.L = p->L;
+    a.wout_off = p->wout_off;
+    a.bout_off = p->bout_off;
+    a.np = p->np;
+    a.XT = p->XT;
+    a.dy = p->fdy;
+    a.slab = p->fslab;
+    a.lossp = p->flossp;
+    a.loss = loss;
+    if (!grad_out) {
+        p->step += 1;
+        a.c1 = 1.f - std::pow(0.9f, (float)p->step);
+        a.c2 = 1.f - std::pow(0.999f, (float)p->step);
+    } else {
+        a.c1 = a.c2 = 1.f;
+    }
+    a.lr = lr;
+    void* args[] = {&a};
+    HCHK(hipLaunchCooperativeKernel((const void*)k_mlp_train_fused, dim3((unsigned)p->fgrid), dim3(256), args, 0, s));
+    return ME_OK;
+}
+
 static int grad_common(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float* loss,
                        hipStream_t s) {
     if (!p || !x || !t || n <= 0 || n % 64) return me_fail(ME_EINVAL, "batch must be a positive multiple of 64");
@@ -708,9 +1126,18 @@ static int grad_common(me_mlp* p, const float* x, const float* t, const int32_t*
     return ME_OK;
 }
 
+int mlp_set_fused_step(me_mlp* p, int on) {
+    if (!p) return me_fail(ME_EINVAL, "null network");
+    if (on && !(p->width == MLPF_W && p->depth <= FT_MAXDEPTH && p->n_in <= MLP_KPAD && p->fgrid > 0))
+        return me_fail(ME_ESTATE, "the fused step needs width 256, depth <= 4 and n_in <= 32");
+    p->fused = on != 0;
+    return ME_OK;
+}
+
 int mlp_backward(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float* grad_dev,
                  float* loss_dev, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    if (p && x && t && grad_dev && fused_applies(p, n)) return fused_step(p, x, t, idx, n, 0.f, loss_dev, grad_dev, s);
     int rc = grad_common(p, x, t, idx, n, loss_dev, s);
     if (rc != ME_OK) return rc;
     if (grad_dev) HCHK(hipMemcpyAsync(grad_dev, p->grad, p->np * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -720,12 +1147,13 @@ int mlp_backward(me_mlp* p, const float* x, const float* t, const int32_t* idx, 
 int mlp_train_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float lr,
                    float* loss_dev, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    if (p && x && t && fused_applies(p, n)) return fused_step(p, x, t, idx, n, lr, loss_dev, nullptr, s);
     int rc = grad_common(p, x, t, idx, n, loss_dev, s);
     if (rc != ME_OK) return rc;
     p->step += 1;
     const float c1 = 1.f - std::pow(0.9f, (float)p->step), c2 = 1.f - std::pow(0.999f, (float)p->step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, s, p->theta, p->m, p->v, p->grad,
-                       p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf);
+                       p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf, p->d_wbft);
     HCHK(hipGetLastError());
     return ME_OK;
 }
@@ -743,7 +1171,15 @@ int mlp_free(me_mlp* p) {
     f(p->m);
     f(p->v);
     for (auto q : p->wbf) f(q);
+    for (auto q : p->wbft) f(q);
     f(p->d_wbf);
+    f(p->d_wbft);
+    f(p->XT);
+    f(p->HTb);
+    f(p->DZTb);
+    f(p->fslab);
+    f(p->flossp);
+    f(p->fdy);
     delete p;
     return ME_OK;
 }

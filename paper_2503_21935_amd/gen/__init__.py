@@ -26,6 +26,8 @@ LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 # Processes whose colour-flow amplitudes are kept in LDS by a workgroup of
 # waves sharing one program (see coop.py): register window of J per wave.
 COOP_WINDOW = {"gg_ttggg": 16}
+# Processes that also get the multi-channel program (single-diagram weights).
+MULTICHANNEL = {"gg_tt", "gg_ttg", "gg_ttgg"}
 
 
 def generate(outdir: str, processes=None, merge: bool = True) -> dict:
@@ -45,4 +47,12 @@ def generate(outdir: str, processes=None, merge: bool = True) -> dict:
             with open(path, "w") as f:
                 f.write(src)
         info[name] = dict(em.plan.stats(), lcd=em.lcd, ncol=len(em.perms))
+        if name in MULTICHANNEL:
+            mc = GGEmitter(name, n, merge=False, cap=LIVE_CAP[name])
+            src = mc.render_mc()
+            path = os.path.join(outdir, f"proc_{name}_mc.h")
+            old = open(path).read() if os.path.exists(path) else None
+            if old != src:
+                with open(path, "w") as f:
+                    f.write(src)
     return info

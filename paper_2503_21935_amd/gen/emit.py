@@ -445,6 +445,12 @@ class GGEmitter:
             R = self.osym(("R", amp["R"]))
             self.w(f"    const cx<T> a = times_i(x.gT * row_col(row_slash({L}, {self.cur(amp['W'])}), {R}));")
             self.flops += FLOPS["row_slash"] + FLOPS["row_col"] + 2
+        ch = getattr(self, "channel_of", {}).get(idx)
+        if ch is not None:
+            # single-diagram weight: |A|^2 into the denominator, and into the
+            # numerator when this is the event's channel
+            self.w("    { const T w2 = a.r * a.r + a.i * a.i;")
+            self.w(f"      den += w2; num += (chan == {ch}) ? w2 : T(0); }}")
         self.emit_jacc("a", amp["colour"])
         self.w("}")
 
@@ -492,6 +498,106 @@ class GGEmitter:
         f = self.flops
         self.lines, self.flops, self.cap = keep
         return f
+
+    # ------------------------------------------------------------------
+    # single diagrams (multi-channel weights), on the unmerged plan
+    # ------------------------------------------------------------------
+    def _current_desc(self, cid):
+        """Tree descriptor of a current of the unmerged plan, or None if it
+        contains a four-gluon vertex."""
+        c = self.plan.currents[cid]
+        if c.is_leaf:
+            return str(next(iter(c.leaves))), min(c.leaves)
+        (coef, kind, kids, ch), = c.terms
+        if kind != "v3":
+            return None
+        parts = [self._current_desc(k) for k in kids]
+        if any(p is None for p in parts):
+            return None
+        parts.sort(key=lambda t: t[1])
+        return "(" + parts[0][0] + "," + parts[1][0] + ")", min(parts[0][1], parts[1][1])
+
+    def channels(self):
+        """Descriptors of the amplitudes that are single diagrams built from
+        three-point vertices: blocks of gluon trees along the top line from
+        ubar(p3) to v(p4), '|'-separated, each tree as nested '(x,y)' with the
+        part holding the smaller gluon label first.  Returns {amp index: channel}
+        and the descriptor list in channel order."""
+        if self.plan.merge:
+            raise ValueError("channels need the unmerged plan")
+        found = []
+        for i, amp in enumerate(self.plan.amps):
+            if amp["kind"] == "root":
+                (coef, kind, kids, ch), = amp["terms"]
+                if kind != "v3":
+                    continue
+                parts = [self._current_desc(k) for k in kids]
+                if any(p is None for p in parts):
+                    continue
+                parts.sort(key=lambda t: t[1])
+                found.append((i, "(" + parts[0][0] + "," + parts[1][0] + ")"))
+            else:
+                blocks = list(amp["L"]) + [amp["W"]] + list(amp["R"])
+                parts = [self._current_desc(b) for b in blocks]
+                if any(p is None for p in parts):
+                    continue
+                found.append((i, "|".join(p[0] for p in parts)))
+        found.sort(key=lambda t: t[1])
+        return {i: k for k, (i, _) in enumerate(found)}, [d for _, d in found]
+
+    def render_mc(self) -> str:
+        """Header of the multi-channel program: the unmerged plan (one amplitude
+        per Feynman diagram and four-gluon colour channel) accumulating, besides
+        J, the single-diagram sums of |A|^2 over the channels (denominator) and
+        for the event's channel (numerator)."""
+        self.channel_of, descs = self.channels()
+        alg = self.algorithmic_flops()
+        self.lines = []
+        self.flops = 0
+        self.emit_amps()
+        body = self.lines
+        executed = self.flops
+        ext_flops = FLOPS["eps"] * self.n + 2 * FLOPS["spinor"]
+        n = self.n
+        nc = len(self.perms)
+        h = []
+        h.append(f"// Generated by paper_2503_21935_amd.gen for {self.name}: g g -> t tbar + {n - 2} g,")
+        h.append(f"// multi-channel form: {len(self.plan.amps)} single-diagram amplitudes, {len(descs)} channels.")
+        h.append("#pragma once")
+        h.append('#include "me_vertex.h"')
+        h.append('#include "me_process.h"')
+        h.append("")
+        h.append(f"struct proc_{self.name}_mc {{")
+        h.append(f"    static constexpr int npart = {n + 2};")
+        h.append(f"    static constexpr int ngluon = {n};")
+        h.append(f"    static constexpr int ncol = {nc};")
+        h.append(f"    static constexpr int nhel = {1 << (n + 2)};")
+        h.append(f"    static constexpr int lcd = {self.lcd};")
+        h.append(f"    static constexpr int identical = {math.factorial(n - 2)};")
+        h.append(f"    static constexpr int nchan = {len(descs)};")
+        h.append(f"    static constexpr double flops_amp = {alg + ext_flops};  // per helicity, excl. colour")
+        h.append(f"    static constexpr double flops_executed = {executed + ext_flops};")
+        h.append("")
+        h.append("    // One helicity: J as in the merged program, plus sum |A_d|^2 over the")
+        h.append("    // channel diagrams (den) and |A_chan|^2 (num).")
+        h.append("    template <typename T, bool TRACK = false>")
+        h.append(f"    static MEV void amps(gg_ext<T, {n}>& x, cx<T>* __restrict__ J, int chan, T& num, T& den, "
+                 "T* __restrict__ S = nullptr) {")
+        h.extend(body)
+        h.append("    }")
+        h.append("")
+        h.append("    template <typename T>")
+        h.append("    static MEV T colour_sum(const cx<T>* __restrict__ J) {")
+        h.extend(self.emit_colour())
+        h.append("    }")
+        h.append("};")
+        h.append("")
+        h.append(f"// channel descriptors (host side), channel order")
+        h.append(f"static const char* const channel_desc_{self.name}[{len(descs)}] = {{")
+        for d in descs:
+            h.append(f'    "{d}",')
+        h.append("};")
+        return "\n".join(h) + "\n"
 
     def render(self) -> str:
         alg = self.algorithmic_flops()

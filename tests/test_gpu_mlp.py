@@ -194,6 +194,41 @@ def test_adam_three_steps(me_mod, torch_cuda):
     net.close()
 
 
+def test_fused_step_matches_layered(me_mod, torch_cuda):
+    """The one-kernel training step (cooperative, grid-wide barriers) against the
+    layered GEMM path: every gradient entry within 2^-6 of the magnitude sum
+    behind it, the loss to 1e-5, and three Adam steps to the same weights."""
+    torch = torch_cuda
+    x = torch.from_numpy(features_np(process_points("gg_ttgg", 2048, 12))).cuda()
+    t = torch.from_numpy(np.random.default_rng(12).normal(size=2048).astype(np.float32)).cuda()
+    nets = [me_mod.Surrogate(seed=19), me_mod.Surrogate(seed=19)]
+    nets[1].set_fused_step(False)
+    theta = nets[0].get_params().astype(np.float64)
+    (gf, lf), (gl, ll) = [n.backward(x, t) for n in nets]
+    gf, gl = gf.cpu().numpy().astype(np.float64), gl.cpu().numpy().astype(np.float64)
+    _, mag = emulated_grad(theta, features_np(process_points("gg_ttgg", 2048, 12)).astype(np.float64),
+                           t.cpu().numpy().astype(np.float64), magnitudes=True)
+    ratio = np.abs(gf - gl) / np.maximum(mag, 1e-30)
+    print(f"[mlp] fused vs layered gradient: max |diff| / magnitude {ratio.max():.2e}", flush=True)
+    assert ratio.max() < 2.0 ** -6
+    assert abs(lf.item() / ll.item() - 1) < 1e-5
+    perm = torch.from_numpy(np.random.default_rng(13).permutation(2048)[:1024].astype(np.int32)).cuda()
+    for lr in (1e-3, 7e-4, 4e-4):
+        for n in nets:
+            n.train_step(x, t, perm, lr)
+    torch.cuda.synchronize()
+    pf, pl = nets[0].get_params(), nets[1].get_params()
+    # Adam moves each weight by about lr sign(g): entries whose batch sum is
+    # rounding noise may move either way, every other one moves alike
+    d = np.abs(pf.astype(np.float64) - pl)
+    print(f"[mlp] fused vs layered after 3 steps: p99 {np.quantile(d, 0.99):.2e}, p99.9 {np.quantile(d, 0.999):.2e}, "
+          f"max {d.max():.2e}", flush=True)
+    assert np.quantile(d, 0.99) < 1e-5
+    assert d.max() <= 2 * (1e-3 + 7e-4 + 4e-4)
+    for n in nets:
+        n.close()
+
+
 def test_adam_step(me_mod, torch_cuda):
     torch = torch_cuda
     net = me_mod.Surrogate(seed=13)
