@@ -79,6 +79,23 @@ int mlp_train_step(me_mlp *mlp, const float *x, const float *t, const int32_t *i
                    float *loss_dev, void *stream);
 
 /*
+ * mlp_train_steps -- nsteps consecutive Adam steps as above, step st on the
+ * mini-batch {x[idx[st n + j]], t[idx[st n + j]]}, j < n (idx == NULL: rows
+ * st n .. st n + n - 1), with learning rate lr_dev[st].
+ * idx: device int32 [nsteps n] or NULL; lr_dev: device float32 [nsteps];
+ * loss_dev: device float32 [nsteps] (may be NULL), the mean squared error of
+ * each step's batch before its update.  Where the one-kernel step applies
+ * (see mlp_set_fused_step) all steps run in one cooperative launch, with
+ * grid-wide barriers between them; otherwise the steps run one by one after a
+ * synchronising read of lr_dev.  The steps are those of nsteps calls of
+ * mlp_train_step, except that the bias corrections 1 - beta^t are computed on
+ * the device.  Calls on one network must be ordered (one stream): they share
+ * its batch buffers.
+ */
+int mlp_train_steps(me_mlp *mlp, const float *x, const float *t, const int32_t *idx, int64_t n, int64_t nsteps,
+                    const float *lr_dev, float *loss_dev, void *stream);
+
+/*
  * mlp_backward -- gradient of the batch loss only (no update), for checks
  * (backpropagation through the network defined above).
  * grad_dev: device float32 [n_params] (flat layout); loss_dev as above.

@@ -400,6 +400,7 @@ def _mlp_sigs(L):
     L.mlp_set_params.argtypes = [vp, ctypes.POINTER(ctypes.c_float), i64]
     L.mlp_forward.argtypes = [vp, vp, i64, vp, vp]
     L.mlp_train_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, vp]
+    L.mlp_train_steps.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
     L.mlp_backward.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp]
     L.mlp_free.argtypes = [vp]
     L.mlp_set_fused_step.argtypes = [vp, ctypes.c_int]
@@ -474,6 +475,24 @@ def mlp_train_step(h, x, t, idx, n, lr, loss=None, stream=None) -> None:
            "mlp_train_step")
 
 
+def mlp_train_steps(h, x, t, idx, n, lr, loss=None, stream=None) -> None:
+    """len(lr) consecutive Adam steps of batch n: step s on rows idx[s n:(s+1) n]
+    (idx None: rows s n ..); lr a device float32 tensor of per-step rates; loss
+    None or a device float32 tensor of one entry per step."""
+    n = int(n)
+    nsteps = _nevt(lr.numel())
+    if idx is not None:
+        _need(idx, n * nsteps, "idx")
+    else:
+        _need(x, n * nsteps * mlp_dims(h)[0], "x")
+        _need(t, n * nsteps, "t")
+    _need(loss, nsteps, "loss")
+    _check(_mlp_sigs(lib()).mlp_train_steps(h, _dev_ptr(x, "float32", "x"), _dev_ptr(t, "float32", "t"),
+                                            _opt_ptr(idx, "int32", "idx"), n, nsteps,
+                                            _dev_ptr(lr, "float32", "lr"), _opt_ptr(loss, "float32", "loss"),
+                                            _stream_handle(stream)), "mlp_train_steps")
+
+
 def mlp_backward(h, x, t, idx, n, grad, loss=None, stream=None) -> None:
     n = _batch_checks(h, x, t, idx, n)
     _need(grad, mlp_n_params(h), "grad")
@@ -543,6 +562,10 @@ class Surrogate:
     def train_step(self, x, t, idx, lr, loss=None, stream=None):
         n = idx.shape[0] if idx is not None else x.shape[0]
         mlp_train_step(self.h, x, t, idx, n, lr, loss, stream)
+
+    def train_steps(self, x, t, idx, n, lr, loss=None, stream=None):
+        """len(lr) steps of batch n in one call (see mlp_train_steps)."""
+        mlp_train_steps(self.h, x, t, idx, n, lr, loss, stream)
 
     def set_fused_step(self, on):
         mlp_set_fused_step(self.h, on)

@@ -1,7 +1,6 @@
 // mlp.hip -- surrogate network kernels: BF16 matrix-core GEMMs with FP32
 // accumulation and fused epilogues, loss, reductions, Adam; the C ABI of
 // include/mlp.h.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -386,11 +385,14 @@ __global__ void k_to_bf16_t(const float* __restrict__ theta, int64_t o, int rows
 // them through every layer forward (activations and pre-activations in LDS),
 // the output layer and loss, and every layer backward down to the first
 // pre-activation gradient, reading the BF16 weights (and their transposes)
-// from L2.  The only cross-row work is the weight and bias gradients, sums
-// over the batch: after the first barrier, phase 2 computes them as GEMMs
-// dW_l = dZ_l^T H_{l-1} on 64 x 64 output tiles, each over a quarter of the
-// batch (partial slabs in a fixed layout), from the transposed activation and
-// gradient copies phase 1 left in global memory (16-byte MFMA fragments).
+// from L2 with all of a layer's loads issued before its first MFMA.  Each
+// tile's activations and gradients also go to global memory transposed
+// ([feature][batch], 32-byte runs per feature written from LDS), and its
+// share of the output layer's gradient to a per-tile partial.  The only
+// cross-row work is the weight and bias gradients, sums over the batch: after
+// the first barrier, phase 2 computes them as GEMMs dW_l = dZ_l^T H_{l-1} on
+// 64 x 64 output tiles, each over a quarter of the batch (partial slabs in a
+// fixed layout), and adds the output layer's per-tile partials per quarter.
 // After the second barrier, phase 3 adds the slabs in a fixed order (the
 // result does not depend on the grid) and applies Adam to the FP32 masters,
 // refreshing the BF16 copies.  Rounding points are those of the layered path.
@@ -417,11 +419,15 @@ struct ft_args {
     bf16* XT;                 // [32][M]
     bf16* HT[FT_MAXDEPTH];    // [256][M]
     bf16* DZT[FT_MAXDEPTH];   // [256][M]
-    float* dy;                // [M]
+    float* opart;             // [257][M / FT_R]: output-layer gradient per tile (weights, then bias)
     float* slab;              // [FT_S][np]
     float* lossp;             // [gridDim.x]
-    float* loss;              // [1] or nullptr
-    float lr, c1, c2;
+    unsigned* bar;            // grid barrier state (zeroed once at allocation)
+    float* loss;              // [nsteps] or nullptr
+    float lr, c1, c2;         // one step (lrs == nullptr): its rate and bias corrections
+    const float* lrs;         // [nsteps] rates of the steps, or nullptr
+    int64_t step0;            // Adam steps taken before this launch
+    int nsteps;               // steps in this launch, batch st on rows idx[st M ..] (or st M ..)
 };
 
 __device__ __forceinline__ float silu_d(float z) {
@@ -429,255 +435,361 @@ __device__ __forceinline__ float silu_d(float z) {
     return s * (1.f + z * (1.f - s));
 }
 
+// B fragments of rows 64 wave + 16 t + 0..15 of the row-major [256][K] matrix
+// Wm (K / 32 MFMA k-steps).  Loaded one layer ahead: the loads of the next
+// product are in flight during the current layer's epilogue.
+template <int K>
+__device__ __forceinline__ void ft_load_w(const bf16* __restrict__ Wm, int wave, int li, int lg, bf16x8 (&b)[8][4]) {
+#pragma unroll
+    for (int ks = 0; ks < K / 32; ++ks)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            b[ks][t] = *reinterpret_cast<const bf16x8*>(Wm + (int64_t)(64 * wave + 16 * t + li) * K + 32 * ks + 8 * lg);
+}
+
+// acc[t] = (16-row LDS tile A, pitch MLPF_PITCH) x (the loaded rows)^T.
+template <int K>
+__device__ __forceinline__ void ft_mma(const bf16* A, const bf16x8 (&b)[8][4], int li, int lg, f32x4 acc[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < K / 32; ++ks) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + li * MLPF_PITCH + 32 * ks + 8 * lg);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[ks][t], acc[t], 0, 0, 0);
+    }
+}
+
+// Grid-wide barrier of a cooperative launch (every block resident).  Each
+// thread waits for its own memory operations, then one thread per block
+// publishes the block's writes (agent-scope release: the L2 write-back),
+// arrives on bar[0] and waits for the generation in bar[32] to move; the last
+// block to arrive resets the count and moves the generation.  One release
+// and one acquire per block, where a fence in every wave would write the L2
+// back once per wave.
+__device__ __forceinline__ void ft_grid_sync(unsigned* bar) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned g = __hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[32], g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            while (__hip_atomic_load(&bar[32], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g)
+                __builtin_amdgcn_s_sleep(1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Column c of the 16-row LDS tile S to dst[c * M + m0 .. + 15] (two 16-byte stores).
+__device__ __forceinline__ void ft_store_t(const bf16* S, int c, bf16* dst, int64_t M, int64_t m0) {
+    bf16x8 v0, v1;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        v0[r] = S[r * MLPF_PITCH + c];
+        v1[r] = S[(8 + r) * MLPF_PITCH + c];
+    }
+    bf16x8* d = reinterpret_cast<bf16x8*>(dst + (int64_t)c * M + m0);
+    d[0] = v0;
+    d[1] = v1;
+}
+
 __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
-    namespace cg = cooperative_groups;
-    cg::grid_group grid = cg::this_grid();
     constexpr int W = MLPF_W, P = MLPF_PITCH;
+    static_assert(FT_R == 16 && W == 256, "one 16-row MFMA tile per phase-1 step, one thread per feature");
     __shared__ __attribute__((aligned(16))) bf16 Hs[FT_R * P];   // layer input / output
     __shared__ __attribute__((aligned(16))) bf16 Gs[FT_R * P];   // pre-activation gradient
     __shared__ float Zs[FT_MAXDEPTH][FT_R][W];                  // pre-activations
-    __shared__ float dys[FT_R];
+    __shared__ float bs[FT_MAXDEPTH][W];                        // hidden biases of this step
+    __shared__ float wos[W + 1];                                // output weights and bias
+    __shared__ float dys[FT_R], tgs[FT_R];
     __shared__ float red[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int64_t M = a.M;
     const int nrt = (int)(M / FT_R);
-    float loss_acc = 0.f;
+    bf16x8 bw0[8][4], bw[8][4];  // first-layer and current-layer B fragments (bw0: one k-step)
+    for (int st = 0; st < a.nsteps; ++st) {
+        const int32_t* idx = a.idx ? a.idx + (int64_t)st * M : nullptr;
+        const float* x = a.idx ? a.x : a.x + (int64_t)st * M * a.n_in;
+        const float* tg = a.idx ? a.t : a.t + (int64_t)st * M;
+        float* loss = a.loss ? a.loss + st : nullptr;
+        const float lr = a.lrs ? a.lrs[st] : a.lr;
+        const float c1 = a.lrs ? 1.f - powf(0.9f, (float)(a.step0 + st + 1)) : a.c1;
+        const float c2 = a.lrs ? 1.f - powf(0.999f, (float)(a.step0 + st + 1)) : a.c2;
+        float loss_acc = 0.f;
+        for (int l = 0; l < a.depth; ++l) bs[l][tid] = a.theta[a.L.b_off[l] + tid];
+        wos[tid] = a.theta[a.wout_off + tid];
+        if (tid == 0) wos[W] = a.theta[a.bout_off];
 
-    // ---------------- phase 1: rows through forward and backward ----------------
-    for (int rt = blockIdx.x; rt < nrt; rt += gridDim.x) {
-        const int64_t m0 = (int64_t)rt * FT_R;
-        for (int e = tid; e < FT_R * MLP_KPAD; e += 256) {
-            const int r = e / MLP_KPAD, k = e % MLP_KPAD;
-            const int64_t src = a.idx ? a.idx[m0 + r] : m0 + r;
-            const bf16 v = (bf16)(k < a.n_in ? a.x[src * a.n_in + k] : 0.f);
-            Hs[r * P + k] = v;
-            a.XT[(int64_t)k * M + m0 + r] = v;
-        }
-        __syncthreads();
-        int K = MLP_KPAD;
-        for (int l = 0; l < a.depth; ++l) {
-            f32x4 acc[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            const bf16* Wl = a.w[l];
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Hs + li * P + k0 + 8 * lg);
+        // ---------------- phase 1: rows through forward and backward ----------------
+        for (int rt = blockIdx.x; rt < nrt; rt += gridDim.x) {
+            const int64_t m0 = (int64_t)rt * FT_R;
+            ft_load_w<MLP_KPAD>(a.w[0], wave, li, lg, bw0);
+            if (a.depth > 1) ft_load_w<W>(a.w[1], wave, li, lg, bw);
+            for (int e = tid; e < FT_R * MLP_KPAD; e += 256) {
+                const int r = e / MLP_KPAD, k = e % MLP_KPAD;
+                const int64_t src = idx ? idx[m0 + r] : m0 + r;
+                Hs[r * P + k] = (bf16)(k < a.n_in ? x[src * a.n_in + k] : 0.f);
+                if (k == 0) tgs[r] = tg[src];
+            }
+            __syncthreads();
+            if (tid < MLP_KPAD) ft_store_t(Hs, tid, a.XT, M, m0);
+            for (int l = 0; l < a.depth; ++l) {
+                f32x4 acc[4];
+                if (l == 0) {
+                    ft_mma<MLP_KPAD>(Hs, bw0, li, lg, acc);
+                } else {
+                    ft_mma<W>(Hs, bw, li, lg, acc);
+                    // the next product's weights: the next layer, or the first backward layer
+                    if (l + 1 < a.depth)
+                        ft_load_w<W>(a.w[l + 1], wave, li, lg, bw);
+                    else
+                        ft_load_w<W>(a.wt[a.depth - 1], wave, li, lg, bw);
+                }
+                __syncthreads();  // the layer input has been read by every wave
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(Wl + (int64_t)(64 * wave + 16 * t + li) * K + k0 + 8 * lg);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                    const int c = 64 * wave + 16 * t + li;
+                    const float bc = bs[l][c];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 4 * lg + v;
+                        const float z = acc[t][v] + bc;
+                        Zs[l][r][c] = z;
+                        Hs[r * P + c] = (bf16)(z * sigmoidf_(z));
+                    }
                 }
+                __syncthreads();
+                ft_store_t(Hs, tid, a.HT[l], M, m0);
             }
-            __syncthreads();  // the layer input has been read by every wave
-            const float* bias = a.theta + a.L.b_off[l];
+            // output layer, residual, loss (16 threads per row)
+            {
+                const int r = tid >> 4, part = tid & 15;
+                const bf16x8* hr = reinterpret_cast<const bf16x8*>(Hs + r * P + part * 16);
+                float s = 0.f;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int c = 64 * wave + 16 * t + li;
-                const float bc = bias[c];
+                for (int k8 = 0; k8 < 2; ++k8) {
+                    const bf16x8 hv = hr[k8];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 4 * lg + v;
-                    const float z = acc[t][v] + bc;
-                    Zs[l][r][c] = z;
-                    const bf16 h = (bf16)(z * sigmoidf_(z));
-                    Hs[r * P + c] = h;
-                    a.HT[l][(int64_t)c * M + m0 + r] = h;
+                    for (int q = 0; q < 8; ++q) s = fmaf((float)hv[q], wos[part * 16 + 8 * k8 + q], s);
+                }
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
+                if (part == 0) {
+                    const float res = s + wos[W] - tgs[r];
+                    dys[r] = 2.f * res / (float)M;
+                    loss_acc += res * res;
                 }
             }
             __syncthreads();
-            K = W;
-        }
-        // output layer, residual, loss, dy (16 threads per row)
-        {
-            const int r = tid >> 4, part = tid & 15;
-            const bf16x8* hr = reinterpret_cast<const bf16x8*>(Hs + r * P + part * 16);
-            const float* wo = a.theta + a.wout_off + part * 16;
-            float s = 0.f;
+            // this tile's share of the output layer's gradient, and dZ of the last hidden layer
+            {
+                const int l = a.depth - 1, c = tid;
+                const float woc = wos[c];
+                float gw = 0.f, gb = 0.f;
 #pragma unroll
-            for (int k8 = 0; k8 < 2; ++k8) {
-                const bf16x8 hv = hr[k8];
-#pragma unroll
-                for (int q = 0; q < 8; ++q) s = fmaf((float)hv[q], wo[8 * k8 + q], s);
-            }
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o);
-            if (part == 0) {
-                const int64_t m = m0 + r;
-                const float y = s + a.theta[a.bout_off];
-                const float res = y - a.t[a.idx ? a.idx[m] : m];
-                const float d = 2.f * res / (float)M;
-                dys[r] = d;
-                a.dy[m] = d;
-                loss_acc += res * res;
-            }
-        }
-        __syncthreads();
-        // dZ of the last hidden layer
-        {
-            const int l = a.depth - 1;
-            const float* wo = a.theta + a.wout_off;
-            for (int e = tid; e < FT_R * W; e += 256) {
-                const int r = e / W, c = e % W;
-                const bf16 g = (bf16)(dys[r] * wo[c] * silu_d(Zs[l][r][c]));
-                Gs[r * P + c] = g;
-                a.DZT[l][(int64_t)c * M + m0 + r] = g;
-            }
-        }
-        __syncthreads();
-        // backward through the hidden layers: dZ_{l-1} = (dZ_l W_l) silu'(Z_{l-1})
-        for (int l = a.depth - 1; l >= 1; --l) {
-            f32x4 acc[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            const bf16* WT = a.wt[l];  // [k][n]
-            for (int n0 = 0; n0 < W; n0 += 32) {
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Gs + li * P + n0 + 8 * lg);
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(WT + (int64_t)(64 * wave + 16 * t + li) * W + n0 + 8 * lg);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                for (int r = 0; r < FT_R; ++r) {
+                    gw = fmaf(dys[r], (float)Hs[r * P + c], gw);
+                    gb += dys[r];
+                    Gs[r * P + c] = (bf16)(dys[r] * woc * silu_d(Zs[l][r][c]));
                 }
-            }
-            __syncthreads();  // Gs has been read by every wave
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int k = 64 * wave + 16 * t + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 4 * lg + v;
-                    const bf16 g = (bf16)(acc[t][v] * silu_d(Zs[l - 1][r][k]));
-                    Gs[r * P + k] = g;
-                    a.DZT[l - 1][(int64_t)k * M + m0 + r] = g;
-                }
+                a.opart[(int64_t)c * nrt + rt] = gw;
+                if (c == 0) a.opart[(int64_t)W * nrt + rt] = gb;
             }
             __syncthreads();
+            ft_store_t(Gs, tid, a.DZT[a.depth - 1], M, m0);
+            // backward through the hidden layers: dZ_{l-1} = (dZ_l W_l) silu'(Z_{l-1})
+            for (int l = a.depth - 1; l >= 1; --l) {
+                f32x4 acc[4];
+                ft_mma<W>(Gs, bw, li, lg, acc);
+                if (l > 1) ft_load_w<W>(a.wt[l - 1], wave, li, lg, bw);
+                __syncthreads();  // Gs has been read by every wave
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = 64 * wave + 16 * t + li;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 4 * lg + v;
+                        Gs[r * P + k] = (bf16)(acc[t][v] * silu_d(Zs[l - 1][r][k]));
+                    }
+                }
+                __syncthreads();
+                ft_store_t(Gs, tid, a.DZT[l - 1], M, m0);
+            }
+            __syncthreads();  // Hs and Gs are rewritten by the next tile
         }
-    }
-    red[tid] = loss_acc;
-    __syncthreads();
-    if (tid == 0) {
-        float s = 0.f;
-        for (int i = 0; i < 256; ++i) s += red[i];
-        a.lossp[blockIdx.x] = s;
-    }
-    __threadfence();
-    grid.sync();
-
-    // ---------------- phase 2: batch sums (weight and bias gradients) ----------------
-    if (blockIdx.x == 0 && a.loss) {
+        red[tid] = loss_acc;
+        __syncthreads();
         if (tid == 0) {
             float s = 0.f;
-            for (int i = 0; i < (int)gridDim.x; ++i) s += a.lossp[i];
-            a.loss[0] = s / (float)M;
+            for (int i = 0; i < 256; ++i) s += red[i];
+            a.lossp[blockIdx.x] = s;
         }
-    }
-    const int64_t span = M / FT_S;
-    // items: for each split s: per layer l, 4 n-blocks x nkb(l) k-blocks of 64, then one output-layer item
-    int per_split = 1;
-    for (int l = 0; l < a.depth; ++l) per_split += 4 * ((a.L.fan_in[l] + 63) / 64);
-    const int nitems = per_split * FT_S;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const int s = it / per_split;
-        int j = it % per_split;
-        const int64_t mb = (int64_t)s * span;
-        float* slab = a.slab + (int64_t)s * a.np;
-        if (j == per_split - 1) {
-            // output layer: dw_out[k] = sum_m dy[m] H_last[m][k], db_out = sum_m dy[m]
-            const bf16* HT = a.HT[a.depth - 1];
-            const int k = tid;
-            float acc = 0.f;
-            for (int64_t m = mb; m < mb + span; m += 8) {
-                const bf16x8 hv = *reinterpret_cast<const bf16x8*>(HT + (int64_t)k * M + m);
-#pragma unroll
-                for (int q = 0; q < 8; ++q) acc = fmaf(a.dy[m + q], (float)hv[q], acc);
-            }
-            slab[a.wout_off + k] = acc;
+        ft_grid_sync(a.bar);
+
+        // ---------------- phase 2: batch sums (weight and bias gradients) ----------------
+        if (blockIdx.x == 0 && loss) {
             if (tid == 0) {
-                float d = 0.f;
-                for (int64_t m = mb; m < mb + span; ++m) d += a.dy[m];
-                slab[a.bout_off] = d;
+                float s = 0.f;
+                for (int i = 0; i < (int)gridDim.x; ++i) s += a.lossp[i];
+                loss[0] = s / (float)M;
             }
-            continue;
         }
-        int l = 0;
-        for (; l < a.depth; ++l) {
-            const int nl = 4 * ((a.L.fan_in[l] + 63) / 64);
-            if (j < nl) break;
-            j -= nl;
-        }
-        const int nkb = (a.L.fan_in[l] + 63) / 64;
-        const int nb = j / nkb, kb = j % nkb;
-        const int fi = a.L.fan_in[l];
-        const int kw = (l == 0) ? MLP_KPAD : W;  // rows of the transposed input copy
-        const bf16* A = a.DZT[l];                // [n][m]
-        const bf16* B = (l == 0) ? a.XT : a.HT[l - 1];  // [k][m]
-        const int n0 = 64 * nb + 16 * wave;
-        const int ntile = min(4, (min(kw, 64 * kb + 64) - 64 * kb) / 16);
-        f32x4 acc[4];
+        const int64_t span = M / FT_S;
+        // items: for each split s: per layer l, 4 n-blocks x nkb(l) k-blocks of 64, then four output-layer items
+        int per_split = 4;
+        for (int l = 0; l < a.depth; ++l) per_split += 4 * ((a.L.fan_in[l] + 63) / 64);
+        const int nitems = per_split * FT_S;
+        for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+            const int s = it / per_split;
+            int j = it % per_split;
+            const int64_t mb = (int64_t)s * span;
+            float* slab = a.slab + (int64_t)s * a.np;
+            if (j >= per_split - 4) {
+                // output layer, columns 64 oq .. 64 oq + 63 (the last item also takes
+                // the bias): four threads per column add this quarter's per-tile
+                // partials in a fixed interleave, then combine by shuffles
+                const int oq = j - (per_split - 4), tpq = nrt / FT_S;
+                const int c = 64 * oq + (tid >> 2), q = tid & 3;
+                const float* src = a.opart + (int64_t)c * nrt + (int64_t)s * tpq;
+                float acc = 0.f;
+#pragma unroll 16
+                for (int i = q; i < tpq; i += 4) acc += src[i];
+                acc += __shfl_xor(acc, 1);
+                acc += __shfl_xor(acc, 2);
+                if (q == 0) slab[a.wout_off + c] = acc;
+                if (oq == 3 && wave == 0) {
+                    const float* sb = a.opart + (int64_t)W * nrt + (int64_t)s * tpq;
+                    float d = 0.f;
+#pragma unroll 16
+                    for (int i = lane & 3; i < tpq; i += 4) d += sb[i];
+                    d += __shfl_xor(d, 1);
+                    d += __shfl_xor(d, 2);
+                    if (lane == 0) slab[a.bout_off] = d;
+                }
+                continue;
+            }
+            int l = 0;
+            for (; l < a.depth; ++l) {
+                const int nl = 4 * ((a.L.fan_in[l] + 63) / 64);
+                if (j < nl) break;
+                j -= nl;
+            }
+            const int nkb = (a.L.fan_in[l] + 63) / 64;
+            const int nb = j / nkb, kb = j % nkb;
+            const int fi = a.L.fan_in[l];
+            const int kw = (l == 0) ? MLP_KPAD : W;  // rows of the transposed input copy
+            const bf16* A = a.DZT[l];                // [n][m]
+            const bf16* B = (l == 0) ? a.XT : a.HT[l - 1];  // [k][m]
+            const int n0 = 64 * nb + 16 * wave;
+            const int ntile = min(4, (min(kw, 64 * kb + 64) - 64 * kb) / 16);
+            f32x4 acc[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float bsum = 0.f;
-        for (int64_t m = mb; m < mb + span; m += 32) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8*>(A + (int64_t)(n0 + li) * M + m + 8 * lg);
-            if (kb == 0) {
+            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            float bsum = 0.f;
+            // rows k beyond the input copy (first layer, second k-tile pair) read a
+            // valid row instead; their products are not stored
+            const bf16* Brow[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Brow[t] = B + (int64_t)min(64 * kb + 16 * t + li, kw - 1) * M + 8 * lg;
+            const bf16* Arow = A + (int64_t)(n0 + li) * M + 8 * lg;
+            auto mstep = [&](const bf16x8& av, const bf16x8 (&bv)[4]) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) bsum += (float)av[q];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[t], 0, 0, 0);
+            };
+            constexpr int U = 8;  // batch steps whose loads are all in flight together
+            int64_t m = mb;
+            for (; m + 32 * U <= mb + span; m += 32 * U) {
+                bf16x8 av[U], bv[U][4];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    av[u] = *reinterpret_cast<const bf16x8*>(Arow + m + 32 * u);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) bv[u][t] = *reinterpret_cast<const bf16x8*>(Brow[t] + m + 32 * u);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) mstep(av[u], bv[u]);
+            }
+            for (; m < mb + span; m += 32) {
+                bf16x8 bv[4];
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Arow + m);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) bv[t] = *reinterpret_cast<const bf16x8*>(Brow[t] + m);
+                mstep(av, bv);
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
-                if (t < ntile) {
-                    const int k = 64 * kb + 16 * t + li;
-                    const bf16x8 b = *reinterpret_cast<const bf16x8*>(B + (int64_t)k * M + m + 8 * lg);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc[t], 0, 0, 0);
+                if (t >= ntile) continue;
+                const int k = 64 * kb + 16 * t + li;
+                if (k >= fi) continue;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int n = n0 + 4 * lg + v;
+                    slab[a.L.w_off[l] + (int64_t)n * fi + k] = acc[t][v];
+                }
+            }
+            if (kb == 0) {
+                bsum += __shfl_xor(bsum, 16);
+                bsum += __shfl_xor(bsum, 32);
+                if (lg == 0) slab[a.L.b_off[l] + n0 + li] = bsum;
+            }
+        }
+        ft_grid_sync(a.bar);
+
+        // ---------------- phase 3: sum the slabs, Adam, BF16 copies ----------------
+        // four parameters per thread per pass, every load of a pass issued first
+        const int64_t stride = (int64_t)gridDim.x * 256;
+        for (int64_t i0 = (int64_t)blockIdx.x * 256 + tid; i0 < a.np; i0 += 4 * stride) {
+            float g[4], mo[4], vo[4], th[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t i = i0 + j * stride;
+                g[j] = mo[j] = vo[j] = th[j] = 0.f;
+                if (i < a.np) {
+#pragma unroll
+                    for (int s = 0; s < FT_S; ++s) g[j] += a.slab[(int64_t)s * a.np + i];
+                    if (!a.grad_out) {
+                        mo[j] = a.m[i];
+                        vo[j] = a.v[i];
+                        th[j] = a.theta[i];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t i = i0 + j * stride;
+                if (i >= a.np) break;
+                if (a.grad_out) {
+                    a.grad_out[i] = g[j];
+                    continue;
+                }
+                const float mi = 0.9f * mo[j] + 0.1f * g[j];
+                const float vi = 0.999f * vo[j] + 0.001f * g[j] * g[j];
+                a.m[i] = mi;
+                a.v[i] = vi;
+                const float t2 = th[j] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+                a.theta[i] = t2;
+                for (int l = 0; l < a.depth; ++l) {
+                    const int64_t o = a.L.w_off[l];
+                    const int fi = a.L.fan_in[l];
+                    if (i >= o && i < o + (int64_t)W * fi) {
+                        const int r = (int)(i - o) / fi, k = (int)(i - o) % fi;
+                        const int ld = (l == 0) ? MLP_KPAD : fi;
+                        a.wbf[l][r * ld + k] = (bf16)t2;
+                        if (l > 0) a.wbft[l][k * W + r] = (bf16)t2;
+                    }
                 }
             }
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (t >= ntile) continue;
-            const int k = 64 * kb + 16 * t + li;
-            if (k >= fi) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int n = n0 + 4 * lg + v;
-                slab[a.L.w_off[l] + (int64_t)n * fi + k] = acc[t][v];
-            }
-        }
-        if (kb == 0) {
-            bsum += __shfl_xor(bsum, 16);
-            bsum += __shfl_xor(bsum, 32);
-            if (lg == 0) slab[a.L.b_off[l] + n0 + li] = bsum;
-        }
-    }
-    __threadfence();
-    grid.sync();
-
-    // ---------------- phase 3: sum the slabs, Adam, BF16 copies ----------------
-    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < a.np; i += (int64_t)gridDim.x * 256) {
-        float g = 0.f;
-#pragma unroll
-        for (int s = 0; s < FT_S; ++s) g += a.slab[(int64_t)s * a.np + i];
-        if (a.grad_out) {
-            a.grad_out[i] = g;
-            continue;
-        }
-        const float mi = 0.9f * a.m[i] + 0.1f * g;
-        const float vi = 0.999f * a.v[i] + 0.001f * g * g;
-        a.m[i] = mi;
-        a.v[i] = vi;
-        const float th = a.theta[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + 1e-8f);
-        a.theta[i] = th;
-        for (int l = 0; l < a.depth; ++l) {
-            const int64_t o = a.L.w_off[l];
-            const int fi = a.L.fan_in[l];
-            if (i >= o && i < o + (int64_t)W * fi) {
-                const int64_t r = (i - o) / fi, k = (i - o) % fi;
-                const int ld = (l == 0) ? MLP_KPAD : fi;
-                a.wbf[l][r * ld + k] = (bf16)th;
-                if (l > 0) a.wbft[l][k * W + r] = (bf16)th;
-            }
-        }
+        if (st + 1 < a.nsteps) ft_grid_sync(a.bar);  // the next step reads the updated weights
     }
 }
 
@@ -709,7 +821,8 @@ struct me_mlp {
     int fgrid;               // its grid: co-resident blocks
     int64_t fcap;            // batch capacity of its buffers
     bf16 *XT, *HTb, *DZTb;   // transposed input, activations and gradients [feature][batch]
-    float *fslab, *flossp, *fdy;
+    float *fslab, *flossp, *fopart;
+    unsigned* fbar;          // grid barrier state of the fused kernel
     int64_t cap;             // activation capacity (rows)
     bf16* X;
     std::vector<bf16*> H;
@@ -1048,9 +1161,11 @@ static int ensure_fused(me_mlp* p, int64_t M) {
     f(p->DZTb);
     f(p->fslab);
     f(p->flossp);
-    f(p->fdy);
+    f(p->fopart);
+    f(p->fbar);
+    p->fbar = nullptr;
     p->XT = p->HTb = p->DZTb = nullptr;
-    p->fslab = p->flossp = p->fdy = nullptr;
+    p->fslab = p->flossp = p->fopart = nullptr;
     p->fcap = 0;
     const int64_t W = p->width;
     HCHK(hipMalloc(&p->XT, MLP_KPAD * M * sizeof(bf16)));
@@ -1058,7 +1173,9 @@ static int ensure_fused(me_mlp* p, int64_t M) {
     HCHK(hipMalloc(&p->DZTb, p->depth * W * M * sizeof(bf16)));
     HCHK(hipMalloc(&p->fslab, FT_S * p->np * sizeof(float)));
     HCHK(hipMalloc(&p->flossp, p->fgrid * sizeof(float)));
-    HCHK(hipMalloc(&p->fdy, M * sizeof(float)));
+    HCHK(hipMalloc(&p->fopart, (W + 1) * (M / FT_R) * sizeof(float)));
+    HCHK(hipMalloc(&p->fbar, 64 * sizeof(unsigned)));
+    HCHK(hipMemset(p->fbar, 0, 64 * sizeof(unsigned)));
     p->fcap = M;
     return ME_OK;
 }
@@ -1067,10 +1184,11 @@ static bool fused_applies(const me_mlp* p, int64_t n) {
     return p->fused && n >= FT_S * 32 && n % (FT_S * 32) == 0 && n <= (int64_t)1 << 24;
 }
 
-// One training step (grad_out == nullptr) or the gradient only, as the fused
-// cooperative kernel.
-static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float lr,
-                      float* loss, float* grad_out, hipStream_t s) {
+// nsteps training steps (grad_out == nullptr; rates lr_dev[nsteps] on the
+// device, or lr for a single step) or the gradient only, as one launch of the
+// fused cooperative kernel.
+static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, int64_t nsteps,
+                      float lr, const float* lr_dev, float* loss, float* grad_out, hipStream_t s) {
     int rc = ensure_fused(p, n);
     if (rc != ME_OK) return rc;
     ft_args a{};
@@ -1097,18 +1215,22 @@ static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* 
     a.bout_off = p->bout_off;
     a.np = p->np;
     a.XT = p->XT;
-    a.dy = p->fdy;
+    a.opart = p->fopart;
     a.slab = p->fslab;
     a.lossp = p->flossp;
+    a.bar = p->fbar;
     a.loss = loss;
+    a.nsteps = (int)nsteps;
+    a.step0 = p->step;
+    a.lrs = lr_dev;
+    a.lr = lr;
     if (!grad_out) {
-        p->step += 1;
-        a.c1 = 1.f - std::pow(0.9f, (float)p->step);
-        a.c2 = 1.f - std::pow(0.999f, (float)p->step);
+        a.c1 = 1.f - std::pow(0.9f, (float)(p->step + 1));
+        a.c2 = 1.f - std::pow(0.999f, (float)(p->step + 1));
+        p->step += nsteps;
     } else {
         a.c1 = a.c2 = 1.f;
     }
-    a.lr = lr;
     void* args[] = {&a};
     HCHK(hipLaunchCooperativeKernel((const void*)k_mlp_train_fused, dim3((unsigned)p->fgrid), dim3(256), args, 0, s));
     return ME_OK;
@@ -1137,7 +1259,8 @@ int mlp_set_fused_step(me_mlp* p, int on) {
 int mlp_backward(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float* grad_dev,
                  float* loss_dev, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (p && x && t && grad_dev && fused_applies(p, n)) return fused_step(p, x, t, idx, n, 0.f, loss_dev, grad_dev, s);
+    if (p && x && t && grad_dev && fused_applies(p, n))
+        return fused_step(p, x, t, idx, n, 1, 0.f, nullptr, loss_dev, grad_dev, s);
     int rc = grad_common(p, x, t, idx, n, loss_dev, s);
     if (rc != ME_OK) return rc;
     if (grad_dev) HCHK(hipMemcpyAsync(grad_dev, p->grad, p->np * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1147,7 +1270,7 @@ int mlp_backward(me_mlp* p, const float* x, const float* t, const int32_t* idx, 
 int mlp_train_step(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, float lr,
                    float* loss_dev, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    if (p && x && t && fused_applies(p, n)) return fused_step(p, x, t, idx, n, lr, loss_dev, nullptr, s);
+    if (p && x && t && fused_applies(p, n)) return fused_step(p, x, t, idx, n, 1, lr, nullptr, loss_dev, nullptr, s);
     int rc = grad_common(p, x, t, idx, n, loss_dev, s);
     if (rc != ME_OK) return rc;
     p->step += 1;
@@ -1155,6 +1278,27 @@ int mlp_train_step(me_mlp* p, const float* x, const float* t, const int32_t* idx
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, s, p->theta, p->m, p->v, p->grad,
                        p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf, p->d_wbft);
     HCHK(hipGetLastError());
+    return ME_OK;
+}
+
+int mlp_train_steps(me_mlp* p, const float* x, const float* t, const int32_t* idx, int64_t n, int64_t nsteps,
+                    const float* lr_dev, float* loss_dev, void* stream) {
+    if (!p || !x || !t || !lr_dev || nsteps < 0 || nsteps > INT32_MAX)
+        return me_fail(ME_EINVAL, "mlp_train_steps: null argument or bad step count");
+    if (nsteps == 0) return ME_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (fused_applies(p, n)) return fused_step(p, x, t, idx, n, nsteps, 0.f, lr_dev, loss_dev, nullptr, s);
+    // layered path: one step at a time, rates read back first
+    std::vector<float> lr((size_t)nsteps);
+    HCHK(hipStreamSynchronize(s));
+    HCHK(hipMemcpy(lr.data(), lr_dev, nsteps * sizeof(float), hipMemcpyDeviceToHost));
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const int32_t* ix = idx ? idx + st * n : nullptr;
+        const float* xs = idx ? x : x + st * n * p->n_in;
+        const float* ts = idx ? t : t + st * n;
+        const int rc = mlp_train_step(p, xs, ts, ix, n, lr[st], loss_dev ? loss_dev + st : nullptr, stream);
+        if (rc != ME_OK) return rc;
+    }
     return ME_OK;
 }
 
@@ -1179,7 +1323,8 @@ int mlp_free(me_mlp* p) {
     f(p->DZTb);
     f(p->fslab);
     f(p->flossp);
-    f(p->fdy);
+    f(p->fopart);
+    f(p->fbar);
     delete p;
     return ME_OK;
 }

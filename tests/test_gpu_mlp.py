@@ -229,6 +229,40 @@ def test_fused_step_matches_layered(me_mod, torch_cuda):
         n.close()
 
 
+def test_train_steps_one_launch(me_mod, torch_cuda):
+    """Several Adam steps in one call (one cooperative launch) against the same
+    steps taken one call at a time: per-step losses and final weights agree (the
+    bias corrections are computed on the device there, on the host here), both
+    with an index list and with consecutive row blocks (idx None)."""
+    torch = torch_cuda
+    n, nsteps = 512, 4
+    x = torch.from_numpy(features_np(process_points("gg_ttgg", n * nsteps, 21))).cuda()
+    t = torch.from_numpy(np.random.default_rng(21).normal(size=n * nsteps).astype(np.float32)).cuda()
+    lrs = [1e-3, 8e-4, 6e-4, 3e-4]
+    lr_dev = torch.tensor(lrs, dtype=torch.float32, device="cuda")
+    idx = torch.from_numpy(np.random.default_rng(22).permutation(n * nsteps).astype(np.int32)).cuda()
+    for use_idx in (True, False):
+        a, b = me_mod.Surrogate(seed=23), me_mod.Surrogate(seed=23)
+        la = torch.zeros(nsteps, dtype=torch.float32, device="cuda")
+        lb = torch.zeros(nsteps, dtype=torch.float32, device="cuda")
+        a.train_steps(x, t, idx if use_idx else None, n, lr_dev, la)
+        for s_ in range(nsteps):
+            if use_idx:
+                b.train_step(x, t, idx[s_ * n:(s_ + 1) * n], lrs[s_], lb[s_:s_ + 1])
+            else:
+                b.train_step(x[s_ * n:(s_ + 1) * n], t[s_ * n:(s_ + 1) * n], None, lrs[s_], lb[s_:s_ + 1])
+        torch.cuda.synchronize()
+        pa, pb = a.get_params().astype(np.float64), b.get_params().astype(np.float64)
+        d = np.abs(pa - pb)
+        la, lb = la.cpu().numpy(), lb.cpu().numpy()
+        print(f"[mlp] {nsteps} steps in one launch (idx {use_idx}): max |dw| {d.max():.2e}, "
+              f"losses {la} vs {lb}", flush=True)
+        np.testing.assert_allclose(la, lb, rtol=1e-5)
+        assert d.max() <= 1e-6
+        a.close()
+        b.close()
+
+
 def test_adam_step(me_mod, torch_cuda):
     torch = torch_cuda
     net = me_mod.Surrogate(seed=13)
