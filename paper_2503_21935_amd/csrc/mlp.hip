@@ -338,9 +338,19 @@ struct layer_map {
 
 // Adam with bias correction on the flat FP32 parameters, then the BF16 copies
 // of the weight matrices (first layer padded to 32 inputs).
+// Offset of element (n, k) of a [rows][K] matrix (rows a multiple of 16, K of
+// 32) stored in fragment order: for each 16-row tile and 32-column step the
+// 64 lanes' 16-byte B fragments of v_mfma_f32_16x16x32_bf16 (lane n % 16 +
+// 16 ((k % 32) / 8) holds columns 8 ((k % 32) / 8) .. + 7 of row n) lie
+// contiguously, so one load instruction reads 1 KB in lane order.
+__device__ __forceinline__ int64_t frag_off(int n, int k, int K) {
+    return ((int64_t)((n >> 4) * (K >> 5) + (k >> 5)) * 64 + (n & 15) + 16 * ((k & 31) >> 3)) * 8 + (k & 7);
+}
+
 __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, int64_t np, float lr, float c1, float c2, layer_map L,
-                       int depth, int width, bf16* const* __restrict__ wbf, bf16* const* __restrict__ wbft) {
+                       int depth, int width, bf16* const* __restrict__ wbf, bf16* const* __restrict__ wbft,
+                       bf16* const* __restrict__ wfr, bf16* const* __restrict__ wtfr) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     const float gi = g[i];
@@ -358,7 +368,26 @@ __global__ void k_adam(float* __restrict__ theta, float* __restrict__ m, float* 
             const int ld = (l == 0) ? MLP_KPAD : fi;
             wbf[l][r * ld + k] = (bf16)th;
             if (l > 0) wbft[l][k * width + r] = (bf16)th;
+            if (wfr) {
+                wfr[l][frag_off((int)r, (int)k, ld)] = (bf16)th;
+                if (l > 0) wtfr[l][frag_off((int)k, (int)r, width)] = (bf16)th;
+            }
         }
+    }
+}
+
+// Fragment-order copies (see frag_off) of W_l (pads k >= fan_in zero) or, with
+// trans, of W_l^T, from the master parameters.
+__global__ void k_to_bf16_frag(const float* __restrict__ theta, int64_t o, int rows, int fi, int ld, int trans,
+                               bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * ld) return;
+    if (!trans) {
+        const int r = (int)(i / ld), k = (int)(i % ld);
+        out[frag_off(r, k, ld)] = (bf16)(k < fi ? theta[o + (int64_t)r * fi + k] : 0.f);
+    } else {
+        const int k = (int)(i / rows), r = (int)(i % rows);  // row k of W^T, [fi][rows]
+        out[frag_off(k, r, rows)] = (bf16)theta[o + (int64_t)r * fi + k];
     }
 }
 
@@ -407,18 +436,18 @@ struct ft_args {
     const int32_t* idx;       // batch rows (nullptr: the first M)
     int64_t M;                // batch size (multiple of FT_S * 32)
     int n_in, depth;
-    const bf16* w[FT_MAXDEPTH];   // [256][ld] (ld 32 for the first layer)
-    const bf16* wt[FT_MAXDEPTH];  // transposed copies [fan_in][256] (layers >= 1)
-    bf16* wbf[FT_MAXDEPTH];       // BF16 copies to refresh after the update
+    bf16* wfr[FT_MAXDEPTH];   // W_l [256][ld] in fragment order (ld 32 for the first layer)
+    bf16* wtfr[FT_MAXDEPTH];  // W_l^T [fan_in][256] in fragment order (layers >= 1)
+    bf16* wbf[FT_MAXDEPTH];   // row-major BF16 copies (other kernels), refreshed with them
     bf16* wbft[FT_MAXDEPTH];
     float* theta;             // FP32 masters (flat layout)
     float *m, *v;             // Adam moments
     float* grad_out;          // gradient only (no update) when non-null
     layer_map L;
     int64_t wout_off, bout_off, np;
-    bf16* XT;                 // [32][M]
-    bf16* HT[FT_MAXDEPTH];    // [256][M]
-    bf16* DZT[FT_MAXDEPTH];   // [256][M]
+    bf16* XT;                 // [32][M], fragment order with K = M
+    bf16* HT[FT_MAXDEPTH];    // [256][M], the same
+    bf16* DZT[FT_MAXDEPTH];   // [256][M], the same
     float* opart;             // [257][M / FT_R]: output-layer gradient per tile (weights, then bias)
     float* slab;              // [FT_S][np]
     float* lossp;             // [gridDim.x]
@@ -435,16 +464,16 @@ __device__ __forceinline__ float silu_d(float z) {
     return s * (1.f + z * (1.f - s));
 }
 
-// B fragments of rows 64 wave + 16 t + 0..15 of the row-major [256][K] matrix
-// Wm (K / 32 MFMA k-steps).  Loaded one layer ahead: the loads of the next
+// B fragments of rows 64 wave + 16 t + 0..15 of the [256][K] matrix Wm kept in
+// fragment order (K / 32 MFMA k-steps).  Loaded one layer ahead: the loads of the next
 // product are in flight during the current layer's epilogue.
 template <int K>
-__device__ __forceinline__ void ft_load_w(const bf16* __restrict__ Wm, int wave, int li, int lg, bf16x8 (&b)[8][4]) {
+__device__ __forceinline__ void ft_load_w(const bf16* __restrict__ Wm, int wave, int lane, bf16x8 (&b)[8][4]) {
 #pragma unroll
     for (int ks = 0; ks < K / 32; ++ks)
 #pragma unroll
         for (int t = 0; t < 4; ++t)
-            b[ks][t] = *reinterpret_cast<const bf16x8*>(Wm + (int64_t)(64 * wave + 16 * t + li) * K + 32 * ks + 8 * lg);
+            b[ks][t] = *reinterpret_cast<const bf16x8*>(Wm + ((int64_t)((4 * wave + t) * (K / 32) + ks) * 64 + lane) * 8);
 }
 
 // acc[t] = (16-row LDS tile A, pitch MLPF_PITCH) x (the loaded rows)^T.
@@ -486,7 +515,8 @@ __device__ __forceinline__ void ft_grid_sync(unsigned* bar) {
     __syncthreads();
 }
 
-// Column c of the 16-row LDS tile S to dst[c * M + m0 .. + 15] (two 16-byte stores).
+// Column c of the 16-row LDS tile S (batch rows m0 .. m0 + 15) to the
+// [feature][batch] array dst in fragment order with K = M (two 16-byte stores).
 __device__ __forceinline__ void ft_store_t(const bf16* S, int c, bf16* dst, int64_t M, int64_t m0) {
     bf16x8 v0, v1;
 #pragma unroll
@@ -494,9 +524,41 @@ __device__ __forceinline__ void ft_store_t(const bf16* S, int c, bf16* dst, int6
         v0[r] = S[r * MLPF_PITCH + c];
         v1[r] = S[(8 + r) * MLPF_PITCH + c];
     }
-    bf16x8* d = reinterpret_cast<bf16x8*>(dst + (int64_t)c * M + m0);
-    d[0] = v0;
-    d[1] = v1;
+    const int64_t base = ((int64_t)(c >> 4) * (M >> 5) + (m0 >> 5)) * 512 + (c & 15) * 8;
+    const int q = (int)(m0 & 31) >> 3;  // 0 or 2
+    *reinterpret_cast<bf16x8*>(dst + base + 128 * q) = v0;
+    *reinterpret_cast<bf16x8*>(dst + base + 128 * (q + 1)) = v1;
+}
+
+// The 16 input rows (padded to MLP_KPAD features) and targets of the tile at
+// batch row m0 of step st: loaded into registers (two elements per thread),
+// then written to LDS, so that the loads of the next step's first tile can be
+// in flight across the end of the current step.
+struct ft_rows {
+    float xv[2], tv[2];
+};
+
+__device__ __forceinline__ void ft_rows_load(const ft_args& a, int st, int64_t m0, int tid, ft_rows& g) {
+    static_assert(FT_R * MLP_KPAD == 2 * 256, "two elements per thread");
+    const int32_t* idx = a.idx ? a.idx + (int64_t)st * a.M : nullptr;
+    const float* x = a.idx ? a.x : a.x + (int64_t)st * a.M * a.n_in;
+    const float* tg = a.idx ? a.t : a.t + (int64_t)st * a.M;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = tid + 256 * q, r = e / MLP_KPAD, k = e % MLP_KPAD;
+        const int64_t src = idx ? idx[m0 + r] : m0 + r;
+        g.xv[q] = k < a.n_in ? x[src * a.n_in + k] : 0.f;
+        g.tv[q] = k == 0 ? tg[src] : 0.f;
+    }
+}
+
+__device__ __forceinline__ void ft_rows_store(const ft_rows& g, int tid, bf16* Hs, float* tgs) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = tid + 256 * q, r = e / MLP_KPAD, k = e % MLP_KPAD;
+        Hs[r * MLPF_PITCH + k] = (bf16)g.xv[q];
+        if (k == 0) tgs[r] = g.tv[q];
+    }
 }
 
 __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
@@ -514,10 +576,8 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
     const int64_t M = a.M;
     const int nrt = (int)(M / FT_R);
     bf16x8 bw0[8][4], bw[8][4];  // first-layer and current-layer B fragments (bw0: one k-step)
+    bool first_in_lds = false;   // the step's first tile is already in Hs / tgs
     for (int st = 0; st < a.nsteps; ++st) {
-        const int32_t* idx = a.idx ? a.idx + (int64_t)st * M : nullptr;
-        const float* x = a.idx ? a.x : a.x + (int64_t)st * M * a.n_in;
-        const float* tg = a.idx ? a.t : a.t + (int64_t)st * M;
         float* loss = a.loss ? a.loss + st : nullptr;
         const float lr = a.lrs ? a.lrs[st] : a.lr;
         const float c1 = a.lrs ? 1.f - powf(0.9f, (float)(a.step0 + st + 1)) : a.c1;
@@ -530,13 +590,12 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
         // ---------------- phase 1: rows through forward and backward ----------------
         for (int rt = blockIdx.x; rt < nrt; rt += gridDim.x) {
             const int64_t m0 = (int64_t)rt * FT_R;
-            ft_load_w<MLP_KPAD>(a.w[0], wave, li, lg, bw0);
-            if (a.depth > 1) ft_load_w<W>(a.w[1], wave, li, lg, bw);
-            for (int e = tid; e < FT_R * MLP_KPAD; e += 256) {
-                const int r = e / MLP_KPAD, k = e % MLP_KPAD;
-                const int64_t src = idx ? idx[m0 + r] : m0 + r;
-                Hs[r * P + k] = (bf16)(k < a.n_in ? x[src * a.n_in + k] : 0.f);
-                if (k == 0) tgs[r] = tg[src];
+            ft_load_w<MLP_KPAD>(a.wfr[0], wave, lane, bw0);
+            if (a.depth > 1) ft_load_w<W>(a.wfr[1], wave, lane, bw);
+            if (!(first_in_lds && rt == (int)blockIdx.x)) {
+                ft_rows g;
+                ft_rows_load(a, st, m0, tid, g);
+                ft_rows_store(g, tid, Hs, tgs);
             }
             __syncthreads();
             if (tid < MLP_KPAD) ft_store_t(Hs, tid, a.XT, M, m0);
@@ -548,9 +607,9 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
                     ft_mma<W>(Hs, bw, li, lg, acc);
                     // the next product's weights: the next layer, or the first backward layer
                     if (l + 1 < a.depth)
-                        ft_load_w<W>(a.w[l + 1], wave, li, lg, bw);
+                        ft_load_w<W>(a.wfr[l + 1], wave, lane, bw);
                     else
-                        ft_load_w<W>(a.wt[a.depth - 1], wave, li, lg, bw);
+                        ft_load_w<W>(a.wtfr[a.depth - 1], wave, lane, bw);
                 }
                 __syncthreads();  // the layer input has been read by every wave
 #pragma unroll
@@ -608,7 +667,7 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
             for (int l = a.depth - 1; l >= 1; --l) {
                 f32x4 acc[4];
                 ft_mma<W>(Gs, bw, li, lg, acc);
-                if (l > 1) ft_load_w<W>(a.wt[l - 1], wave, li, lg, bw);
+                if (l > 1) ft_load_w<W>(a.wtfr[l - 1], wave, lane, bw);
                 __syncthreads();  // Gs has been read by every wave
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -646,7 +705,14 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
         int per_split = 4;
         for (int l = 0; l < a.depth; ++l) per_split += 4 * ((a.L.fan_in[l] + 63) / 64);
         const int nitems = per_split * FT_S;
-        for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        // Items that share operand rows are neighbours in this order; blocks go
+        // round-robin over the 8 XCDs, so slot v of XCD x takes item x q + v:
+        // each XCD's L2 then fetches about an eighth of the operands instead
+        // of nearly all of them.
+        const int q = (nitems + 7) / 8;
+        for (int vb = blockIdx.x; vb < 8 * q; vb += gridDim.x) {
+            const int it = (vb % 8) * q + vb / 8;
+            if (it >= nitems) continue;
             const int s = it / per_split;
             int j = it % per_split;
             const int64_t mb = (int64_t)s * span;
@@ -693,12 +759,14 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
             float bsum = 0.f;
-            // rows k beyond the input copy (first layer, second k-tile pair) read a
-            // valid row instead; their products are not stored
+            // operands in fragment order: the fragment of 16-row tile f at batch
+            // step m / 32 starts at (f (M / 32) + m / 32) 512; tiles of rows beyond
+            // the input copy (first layer, second tile pair) read a valid tile
+            // instead, and their products are not stored
             const bf16* Brow[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) Brow[t] = B + (int64_t)min(64 * kb + 16 * t + li, kw - 1) * M + 8 * lg;
-            const bf16* Arow = A + (int64_t)(n0 + li) * M + 8 * lg;
+            for (int t = 0; t < 4; ++t) Brow[t] = B + (int64_t)min(4 * kb + t, kw / 16 - 1) * (M >> 5) * 512 + lane * 8;
+            const bf16* Arow = A + (int64_t)(n0 >> 4) * (M >> 5) * 512 + lane * 8;
             auto mstep = [&](const bf16x8& av, const bf16x8 (&bv)[4]) {
 #pragma unroll
                 for (int q = 0; q < 8; ++q) bsum += (float)av[q];
@@ -711,18 +779,18 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
                 bf16x8 av[U], bv[U][4];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    av[u] = *reinterpret_cast<const bf16x8*>(Arow + m + 32 * u);
+                    av[u] = *reinterpret_cast<const bf16x8*>(Arow + 16 * (m + 32 * u));
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) bv[u][t] = *reinterpret_cast<const bf16x8*>(Brow[t] + m + 32 * u);
+                    for (int t = 0; t < 4; ++t) bv[u][t] = *reinterpret_cast<const bf16x8*>(Brow[t] + 16 * (m + 32 * u));
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) mstep(av[u], bv[u]);
             }
             for (; m < mb + span; m += 32) {
                 bf16x8 bv[4];
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Arow + m);
+                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Arow + 16 * m);
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bv[t] = *reinterpret_cast<const bf16x8*>(Brow[t] + m);
+                for (int t = 0; t < 4; ++t) bv[t] = *reinterpret_cast<const bf16x8*>(Brow[t] + 16 * m);
                 mstep(av, bv);
             }
 #pragma unroll
@@ -745,6 +813,10 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
         ft_grid_sync(a.bar);
 
         // ---------------- phase 3: sum the slabs, Adam, BF16 copies ----------------
+        // the next step's first tile, loaded across the Adam pass and the barrier
+        ft_rows nxt;
+        const bool pre = st + 1 < a.nsteps && (int)blockIdx.x < nrt;
+        if (pre) ft_rows_load(a, st + 1, (int64_t)blockIdx.x * FT_R, tid, nxt);
         // four parameters per thread per pass, every load of a pass issued first
         const int64_t stride = (int64_t)gridDim.x * 256;
         for (int64_t i0 = (int64_t)blockIdx.x * 256 + tid; i0 < a.np; i0 += 4 * stride) {
@@ -784,11 +856,17 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
                         const int r = (int)(i - o) / fi, k = (int)(i - o) % fi;
                         const int ld = (l == 0) ? MLP_KPAD : fi;
                         a.wbf[l][r * ld + k] = (bf16)t2;
-                        if (l > 0) a.wbft[l][k * W + r] = (bf16)t2;
+                        a.wfr[l][frag_off(r, k, ld)] = (bf16)t2;
+                        if (l > 0) {
+                            a.wbft[l][k * W + r] = (bf16)t2;
+                            a.wtfr[l][frag_off(k, r, W)] = (bf16)t2;
+                        }
                     }
                 }
             }
         }
+        if (pre) ft_rows_store(nxt, tid, Hs, tgs);
+        first_in_lds = pre;
         if (st + 1 < a.nsteps) ft_grid_sync(a.bar);  // the next step reads the updated weights
     }
 }
@@ -817,6 +895,9 @@ struct me_mlp {
     bf16** d_wbf;            // device array of those pointers
     std::vector<bf16*> wbft; // transposed copies [fan_in][width] (layers >= 1; the backward pass)
     bf16** d_wbft;
+    std::vector<bf16*> wfr;  // fragment-order copies of W_l and W_l^T for the one-kernel step
+    std::vector<bf16*> wtfr; // (width 256 only; empty otherwise)
+    bf16 **d_wfr, **d_wtfr;
     bool fused;              // training step as one cooperative kernel where it applies
     int fgrid;               // its grid: co-resident blocks
     int64_t fcap;            // batch capacity of its buffers
@@ -895,6 +976,13 @@ static hipError_t refresh_bf16(me_mlp* p, hipStream_t s) {
             const int64_t nt = (int64_t)p->width * fi;
             hipLaunchKernelGGL(k_to_bf16_t, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, p->theta,
                                p->L.w_off[l], p->width, fi, p->wbft[l]);
+        }
+        if (p->d_wfr) {
+            hipLaunchKernelGGL(k_to_bf16_frag, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p->theta,
+                               p->L.w_off[l], p->width, fi, ld, 0, p->wfr[l]);
+            if (l > 0)
+                hipLaunchKernelGGL(k_to_bf16_frag, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p->theta,
+                                   p->L.w_off[l], p->width, fi, ld, 1, p->wtfr[l]);
         }
     }
     return hipGetLastError();
@@ -1031,6 +1119,8 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
     p->Z.assign(depth, nullptr);
     p->wbf.assign(depth, nullptr);
     p->wbft.assign(depth, nullptr);
+    p->wfr.assign(depth, nullptr);
+    p->wtfr.assign(depth, nullptr);
     std::vector<float> h(o, 0.f);
     uint64_t st = seed;
     for (int l = 0; l < depth; ++l) {
@@ -1064,6 +1154,17 @@ int mlp_create(int n_in, int width, int depth, uint64_t seed, me_mlp** out) {
     p->fused = (width == MLPF_W && depth <= FT_MAXDEPTH && n_in <= MLP_KPAD);
     p->fgrid = 0;
     if (p->fused) {
+        for (int l = 0; l < depth; ++l) {
+            const int ld = (l == 0) ? MLP_KPAD : p->L.fan_in[l];
+            if (bad(hipMalloc(&p->wfr[l], (size_t)width * ld * sizeof(bf16))) ||
+                (l > 0 && bad(hipMalloc(&p->wtfr[l], (size_t)width * ld * sizeof(bf16)))))
+                return me_fail(ME_ENOMEM, "mlp_create: device allocation");
+        }
+        if (bad(hipMalloc(&p->d_wfr, depth * sizeof(bf16*))) ||
+            bad(hipMemcpy(p->d_wfr, p->wfr.data(), depth * sizeof(bf16*), hipMemcpyHostToDevice)) ||
+            bad(hipMalloc(&p->d_wtfr, depth * sizeof(bf16*))) ||
+            bad(hipMemcpy(p->d_wtfr, p->wtfr.data(), depth * sizeof(bf16*), hipMemcpyHostToDevice)))
+            return me_fail(ME_EDEVICE, "mlp_create: device allocation");
         int dev = 0, cus = 0, per = 0;
         if (bad(hipGetDevice(&dev)) || bad(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) ||
             bad(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_mlp_train_fused, 256, 0)))
@@ -1199,8 +1300,8 @@ static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* 
     a.n_in = p->n_in;
     a.depth = p->depth;
     for (int l = 0; l < p->depth; ++l) {
-        a.w[l] = p->wbf[l];
-        a.wt[l] = p->wbft[l];
+        a.wfr[l] = p->wfr[l];
+        a.wtfr[l] = p->wtfr[l];
         a.wbf[l] = p->wbf[l];
         a.wbft[l] = p->wbft[l];
         a.HT[l] = p->HTb + (int64_t)l * p->width * n;
@@ -1276,7 +1377,7 @@ int mlp_train_step(me_mlp* p, const float* x, const float* t, const int32_t* idx
     p->step += 1;
     const float c1 = 1.f - std::pow(0.9f, (float)p->step), c2 = 1.f - std::pow(0.999f, (float)p->step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, s, p->theta, p->m, p->v, p->grad,
-                       p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf, p->d_wbft);
+                       p->np, lr, c1, c2, p->L, p->depth, p->width, p->d_wbf, p->d_wbft, p->d_wfr, p->d_wtfr);
     HCHK(hipGetLastError());
     return ME_OK;
 }
@@ -1318,6 +1419,10 @@ int mlp_free(me_mlp* p) {
     for (auto q : p->wbft) f(q);
     f(p->d_wbf);
     f(p->d_wbft);
+    for (auto q : p->wfr) f(q);
+    for (auto q : p->wtfr) f(q);
+    f(p->d_wfr);
+    f(p->d_wtfr);
     f(p->XT);
     f(p->HTb);
     f(p->DZTb);
