@@ -12,6 +12,10 @@ Contents
   * ``me2``            |M|^2 per event (C routines in ``me_oracle.c``)
   * ``ordered_amps``   colour-ordered partial amplitudes at one helicity
   * ``me2_dressed``    |M|^2 by explicit colour brute force (slow; few events)
+  * ``channel_diagrams``, ``diagram_sums``  single Feynman diagrams (route 4)
+  * ``qew_me2``, ``qew_amps``  a massless quark line with gluons and a photon/Z
+                        decaying to leptons (route 5; QEW_PROCESSES, among
+                        them the paper's DY+3j subprocess g ubar -> tau+ tau- g g ubar)
 
 The paper gives no formulas; the matrix element is the textbook tree-level one
 (its Sec. 2 names the step, Sec. 3 the two parts -- Feynman diagrams, then the
@@ -84,6 +88,12 @@ def _lib(quad: bool = False):
                                         ctypes.c_double, dp]
     lib.oracle_ggx_dressed.argtypes = [dp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        dp, dp]
+    ip = ctypes.POINTER(ctypes.c_int32)
+    lib.oracle_qew.argtypes = [dp, ctypes.c_int64, ip, dp, dp, ctypes.c_double, dp, dp]
+    lib.oracle_qew_amps.argtypes = [dp, ip, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_qew_externals.argtypes = [dp, ip, dp, ctypes.c_int, dp]
+    lib.oracle_bg_custom.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ip, ctypes.c_int, dp]
     return lib
 
 
@@ -173,6 +183,8 @@ def me2(process: str, mom, params=None, quad: bool = False, per_helicity: bool =
         out = np.empty(n)
         qh = np.empty((n, 16)) if per_helicity else None
         rc = lib.oracle_ee_mumu(_ptr(mom), n, p["e"], p["sw2"], p["mz"], p["wz"], _ptr(out), _ptr(qh))
+    elif process in QEW_PROCESSES:
+        return qew_me2(process, mom, params, quad=quad, per_helicity=per_helicity)
     elif process in PROCESS_NGLUON:
         ng = PROCESS_NGLUON[process]
         mom = _check_mom(mom, ng + 2)
@@ -377,3 +389,135 @@ def rambo(roots: float, masses, seed: int, first: int, n_evt: int, cond: bool = 
     if rc != 0:
         raise ValueError("oracle_rambo: bad arguments")
     return (mom, wt, cd) if cond else (mom, wt)
+
+
+# --------------------------------------------------------------------------
+# Route 5: one massless quark line, gluons and gamma/Z -> lepton pair
+# --------------------------------------------------------------------------
+
+_QEW_DESC = 8 + 2 * _MAXG
+
+# n gluons, particle count, row end (particle, kind: 0 outgoing quark ubar(p),
+# 1 incoming antiquark vbar(p)), column end (particle, kind: 0 outgoing
+# antiquark v(p), 1 incoming quark u(p)), lepton l- and l+ particles, gluons
+# (particle, incoming), (Q, T3) of the quark line and of the leptons, and the
+# average: spins x colours x identical final-state factor.
+QEW_PROCESSES = {
+    # g ubar -> tau+ tau- g g ubar: the paper's DY+3j subprocess (Sec. 3)
+    "gux_taptamggux": dict(n=3, npart=7, row=(1, 1), col=(6, 0), lm=3, lp=2, gluons=((0, 1), (4, 0), (5, 0)),
+                           quark=(2.0 / 3.0, 0.5), lepton=(-1.0, -0.5), avg=4 * 24 * 2),
+    # the same family with fewer gluons
+    "gux_taptamgux": dict(n=2, npart=6, row=(1, 1), col=(5, 0), lm=3, lp=2, gluons=((0, 1), (4, 0)),
+                          quark=(2.0 / 3.0, 0.5), lepton=(-1.0, -0.5), avg=4 * 24),
+    "gux_taptamux": dict(n=1, npart=5, row=(1, 1), col=(4, 0), lm=3, lp=2, gluons=((0, 1),),
+                         quark=(2.0 / 3.0, 0.5), lepton=(-1.0, -0.5), avg=4 * 24),
+    # u ubar -> tau+ tau-: lowest-order Drell-Yan
+    "uux_taptam": dict(n=0, npart=4, row=(1, 1), col=(0, 1), lm=3, lp=2, gluons=(),
+                       quark=(2.0 / 3.0, 0.5), lepton=(-1.0, -0.5), avg=4 * 9),
+}
+
+
+def _qew_spec(process):
+    return QEW_PROCESSES[process] if isinstance(process, str) else process
+
+
+def _qew_arrays(spec, params):
+    p = params or sm_params()
+    desc = np.zeros(_QEW_DESC, dtype=np.int32)
+    desc[:8] = [spec["n"], spec["npart"], spec["row"][0], spec["row"][1], spec["col"][0], spec["col"][1],
+                spec["lm"], spec["lp"]]
+    for a, (pi, inc) in enumerate(spec["gluons"]):
+        desc[8 + a] = pi
+        desc[8 + _MAXG + a] = inc
+    cpl = np.array([p["e"], p["sw2"], p["mz"], p["wz"], p["gs"], *spec["quark"], *spec["lepton"]],
+                   dtype=np.float64)
+    return desc, cpl
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def qew_colour(n: int) -> np.ndarray:
+    """Colour matrix of a quark line with n gluons (n = 0: sum_ij delta_ij delta_ij = 3)."""
+    return np.array([[3.0]]) if n == 0 else np.ascontiguousarray(colour_matrix(n))
+
+
+def qew_me2(process, mom, params=None, quad: bool = False, per_helicity: bool = False, colour=None):
+    """|M|^2 per event for a quark line with gluons and a gamma/Z -> lepton pair
+    (``process`` a name in QEW_PROCESSES or a spec of the same form)."""
+    spec = _qew_spec(process)
+    desc, cpl = _qew_arrays(spec, params)
+    mom = _check_mom(mom, spec["npart"])
+    n = mom.shape[0]
+    C = np.ascontiguousarray(qew_colour(spec["n"]) if colour is None else colour, dtype=np.float64)
+    out = np.empty(n)
+    qh = np.empty((n, 1 << spec["npart"])) if per_helicity else None
+    rc = _lib(quad).oracle_qew(_ptr(mom), n, _ip(desc), _ptr(cpl), _ptr(C), 1.0 / spec["avg"], _ptr(out), _ptr(qh))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return (out, qh) if per_helicity else out
+
+
+def qew_amps(process, mom1, hel: int, params=None, gauge_gluon: int = -1, gauge_ew: bool = False,
+             quad: bool = False):
+    """Colour-ordered partial amplitudes (orders of ``orderings(n)``) of one event at one helicity."""
+    spec = _qew_spec(process)
+    desc, cpl = _qew_arrays(spec, params)
+    mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(spec["npart"], 4)
+    out = np.empty((math.factorial(spec["n"]), 2))
+    rc = _lib(quad).oracle_qew_amps(_ptr(mom1), _ip(desc), _ptr(cpl), hel, gauge_gluon, int(gauge_ew), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return out[:, 0] + 1j * out[:, 1]
+
+
+def qew_externals(process, mom1, hel: int, params=None):
+    """External pieces of one event at one helicity: dict of gluon q and eps, the
+    row spinor and its momentum, the column spinor, the insertion's momentum qE
+    and vectors EL, ER (couplings and propagators included)."""
+    spec = _qew_spec(process)
+    desc, cpl = _qew_arrays(spec, params)
+    n = spec["n"]
+    mom1 = np.ascontiguousarray(mom1, dtype=np.float64).reshape(spec["npart"], 4)
+    out = np.empty(4 * n + 8 * n + 4 + 8 + 8 + 4 + 8 + 8)
+    rc = _lib(False).oracle_qew_externals(_ptr(mom1), _ip(desc), _ptr(cpl), hel, _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    o = 0
+
+    def take(k):
+        nonlocal o
+        v = out[o:o + k]
+        o += k
+        return v
+
+    q = take(4 * n).reshape(n, 4)
+    eps = take(8 * n).reshape(n, 4, 2)
+    prow = take(4)
+    row = take(8).reshape(4, 2)
+    col = take(8).reshape(4, 2)
+    qE = take(4)
+    EL = take(8).reshape(4, 2)
+    ER = take(8).reshape(4, 2)
+    c = lambda a: a[..., 0] + 1j * a[..., 1]  # noqa: E731
+    return dict(q=q, eps=c(eps), prow=prow, row=c(row), col=c(col), qE=qE, EL=c(EL), ER=c(ER))
+
+
+def bg_custom(q, eps, prow, row, col, sigma, g, m=0.0, w=0.0, four_gluon: bool = True):
+    """Route 2's colour-ordered amplitude (quark line with gluon-like legs) for
+    explicit externals: q [n][4] incoming-flow momenta, eps [n][4] complex
+    vectors, the row spinor with its momentum, the column spinor; one order."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    n = q.shape[0]
+    e = np.ascontiguousarray(np.stack([np.real(eps), np.imag(eps)], axis=-1), dtype=np.float64)
+    r = np.ascontiguousarray(np.stack([np.real(row), np.imag(row)], axis=-1), dtype=np.float64)
+    c = np.ascontiguousarray(np.stack([np.real(col), np.imag(col)], axis=-1), dtype=np.float64)
+    pr = np.ascontiguousarray(prow, dtype=np.float64)
+    s = np.ascontiguousarray(sigma, dtype=np.int32)
+    out = np.empty(2)
+    rc = _lib(False).oracle_bg_custom(n, _ptr(q), _ptr(e), _ptr(pr), _ptr(r), _ptr(c), m, w, g, _ip(s),
+                                      int(four_gluon), _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle failed")
+    return out[0] + 1j * out[1]

@@ -36,6 +36,13 @@
  *      every colour index explicit (recursion over subsets of gluons with
  *      f^{abc} and Gell-Mann T^a), and |M|^2 summed over all external colour
  *      assignments by brute force.  Independent of route 2's colour algebra.
+ *   4. single Feynman diagrams of g g -> t tbar + (n-2) g (three-point
+ *      vertices only), for the multi-channel weights.
+ *   5. a massless quark line with n gluons and one photon/Z insertion that
+ *      decays to a lepton pair (g ubar -> tau+ tau- g g ubar, the paper's
+ *      DY+3j subprocess, Sec. 3, and its smaller relatives): colour-ordered
+ *      recursion as in route 2 with the colourless insertion placed at every
+ *      point of the quark line.
  *
  * Compiled twice: plain double (liboracle.so) and, with -DORACLE_QUAD,
  * __float128 (liboracle_quad.so) to adjudicate differences near 1e-12.
@@ -912,5 +919,380 @@ int oracle_ggx_diagram_amps(const double *mom1, int n, int h, int ndiag, const i
         out[2 * k] = (double)CREAL(a);
         out[2 * k + 1] = (double)CIMAG(a);
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Route 5: a massless quark line with gluons and one gamma/Z insertion */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Processes with one massless quark line, n gluons and a lepton pair from
+ * gamma/Z, e.g. g ubar -> tau+ tau- g g ubar (the paper's DY+3j subprocess).
+ * Descriptor desc[] (ints): n, npart, row particle, row kind (0 outgoing quark
+ * ubar(p), 1 incoming antiquark vbar(p)), column particle, column kind (0
+ * outgoing antiquark v(p), 1 incoming quark u(p)), l- particle, l+ particle,
+ * then MAXG gluon particle indices and MAXG incoming flags.  Couplings cpl[]:
+ * e, sin^2 theta_W, M_Z, Gamma_Z, g_s, Q and T3 of the quark, Q and T3 of the
+ * lepton.  All fermions massless.
+ *
+ * Rules: quark-gluon i g_s gamma^mu T^a (colour-ordered: i g_s gamma^mu);
+ * photon -i e Q gamma^mu; Z -i g_Z gamma^mu (gL PL + gR PR) with g_Z =
+ * e/(s_W c_W), gL = T3 - Q s_W^2, gR = -Q s_W^2; photon propagator -i g/k^2;
+ * Z propagator -i g/(k^2 - M_Z^2 + i M_Z Gamma_Z) (the k k / M_Z^2 term drops
+ * against the conserved massless lepton current); quark propagator
+ * i pslash / p^2.  The boson and lepton pair fold into one insertion on the
+ * quark line, gamma^mu (EL_mu PL + ER_mu PR) with
+ *   EX = i e^2 Qq Ql Jg / k^2 + i g_Z^2 gX(q) JZ / (k^2 - M_Z^2 + i M_Z Gamma_Z),
+ *   Jg^mu = ubar(l-) gamma^mu v(l+),  JZ^mu = ubar(l-) gamma^mu (gL(l) PL + gR(l) PR) v(l+),
+ * k = p(l-) + p(l+).  The insertion is a colour singlet, so the colour
+ * decomposition is that of the quark line with n gluons.
+ */
+#define QEW_DESC (8 + 2 * MAXG)
+
+typedef struct {
+    int n;
+    real q[MAXG][4];   /* incoming-flow gluon momenta */
+    cplx eps[MAXG][4];
+    real prow[4];      /* momentum along the fermion flow leaving the row end */
+    cplx row[4], col[4];
+    cplx GE[4][4];     /* the gamma/Z insertion as a Dirac matrix */
+    real qE[4];        /* momentum flowing into the line at the insertion */
+    real gs;
+} qew_ext;
+
+static void qew_setup(const real *mom, const int *d, const double *cpl, int h, int gauge_gluon, int gauge_ew,
+                      qew_ext *X) {
+    const int n = d[0], np = d[1];
+    const int *gp = d + 8, *gin = d + 8 + MAXG;
+    X->n = n;
+    X->gs = cpl[4];
+#define HEL(i) ((((h) >> (np - 1 - (i))) & 1) ? 1 : -1)
+    for (int a = 0; a < n; ++a) {
+        const real *p = mom + 4 * gp[a];
+        const int incoming = gin[a];
+        cplx e[4];
+        eps_vec(p, HEL(gp[a]), e);
+        for (int mu = 0; mu < 4; ++mu) {
+            X->q[a][mu] = incoming ? p[mu] : -p[mu];
+            X->eps[a][mu] = incoming ? e[mu] : CCONJ(e[mu]);
+        }
+        if (a == gauge_gluon)
+            for (int mu = 0; mu < 4; ++mu) X->eps[a][mu] = X->q[a][mu] / X->q[a][0];
+    }
+    /* quark line ends */
+    {
+        const real *p = mom + 4 * d[2];
+        cplx s[4];
+        if (d[3] == 0) {
+            u_spinor(p, 0, HEL(d[2]), s);
+            for (int mu = 0; mu < 4; ++mu) X->prow[mu] = p[mu];
+        } else {
+            v_spinor(p, 0, HEL(d[2]), s);
+            for (int mu = 0; mu < 4; ++mu) X->prow[mu] = -p[mu];
+        }
+        bar(s, X->row);
+        const real *pc = mom + 4 * d[4];
+        if (d[5] == 0)
+            v_spinor(pc, 0, HEL(d[4]), X->col);
+        else
+            u_spinor(pc, 0, HEL(d[4]), X->col);
+    }
+    /* lepton pair and the gamma/Z insertion */
+    const real *pm = mom + 4 * d[6], *pp = mom + 4 * d[7];
+    cplx um[4], ubm[4], vp[4];
+    u_spinor(pm, 0, HEL(d[6]), um);
+    bar(um, ubm);
+    v_spinor(pp, 0, HEL(d[7]), vp);
+#undef HEL
+    const real e = cpl[0], sw2 = cpl[1], mz = cpl[2], wz = cpl[3];
+    const real Qq = cpl[5], T3q = cpl[6], Ql = cpl[7], T3l = cpl[8];
+    const real gz = e / RSQRT(sw2 * (1 - sw2));
+    const real gLq = T3q - Qq * sw2, gRq = -Qq * sw2, gLl = T3l - Ql * sw2, gRl = -Ql * sw2;
+    real k[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        k[mu] = pm[mu] + pp[mu];
+        X->qE[mu] = -k[mu];
+    }
+    const real k2 = rdot(k, k);
+    const cplx dz = (k2 - mz * mz) + CI * (mz * wz);
+    cplx Jg[4], JZ[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        cplx Cl[4][4], t[4];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                cplx acc = 0;
+                for (int l = 0; l < 4; ++l) {
+                    const cplx pl = ((l == j ? 1 : 0) - G5[l][j]) / 2, pr = ((l == j ? 1 : 0) + G5[l][j]) / 2;
+                    acc += G[mu][i][l] * (gLl * pl + gRl * pr);
+                }
+                Cl[i][j] = acc;
+            }
+        row_mat(ubm, G[mu], t);
+        Jg[mu] = row_col(t, vp);
+        row_mat(ubm, Cl, t);
+        JZ[mu] = row_col(t, vp);
+    }
+    cplx EL[4], ER[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        const cplx ga = CI * e * e * Qq * Ql * Jg[mu] / k2;
+        EL[mu] = ga + CI * gz * gz * gLq * JZ[mu] / dz;
+        ER[mu] = ga + CI * gz * gz * gRq * JZ[mu] / dz;
+        if (gauge_ew) EL[mu] = ER[mu] = X->qE[mu];
+    }
+    cplx SL[4][4], SR[4][4];
+    slash_c(EL, SL);
+    slash_c(ER, SR);
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cplx acc = 0;
+            for (int l = 0; l < 4; ++l) {
+                const cplx pl = ((l == j ? 1 : 0) - G5[l][j]) / 2, pr = ((l == j ? 1 : 0) + G5[l][j]) / 2;
+                acc += SL[i][l] * pl + SR[i][l] * pr;
+            }
+            X->GE[i][j] = acc;
+        }
+}
+
+/* Colour-ordered amplitude for gluon order sigma: gluon currents over
+ * contiguous ranges of sigma (three- and four-gluon vertices, as in route 2),
+ * then the quark line from the row end, absorbing the gluon ranges in order
+ * and the colourless insertion at any point: U[m][e] is the row spinor after
+ * the first m gluons of sigma and e insertions, propagator included. */
+static cplx qew_amp(const qew_ext *X, const int *sigma) {
+    const int n = X->n;
+    const real g = X->gs;
+    cplx J[MAXG][MAXG][4];
+    real Q[MAXG][MAXG][4];
+    for (int i = 0; i < n; ++i)
+        for (int mu = 0; mu < 4; ++mu) {
+            J[i][i][mu] = X->eps[sigma[i]][mu];
+            Q[i][i][mu] = X->q[sigma[i]][mu];
+        }
+    for (int len = 2; len <= n; ++len)
+        for (int i = 0; i + len - 1 < n; ++i) {
+            const int j = i + len - 1;
+            for (int mu = 0; mu < 4; ++mu) Q[i][j][mu] = Q[i][i][mu] + Q[i + 1][j][mu];
+            const real Q2 = rdot(Q[i][j], Q[i][j]);
+            cplx acc[4] = {0, 0, 0, 0};
+            for (int k = i; k < j; ++k) {
+                cplx t[4];
+                v3(J[i][k], Q[i][k], J[k + 1][j], Q[k + 1][j], t);
+                for (int mu = 0; mu < 4; ++mu) acc[mu] += (-g / Q2) * t[mu];
+            }
+            for (int k = i; k < j; ++k)
+                for (int l = k + 1; l < j; ++l) {
+                    const cplx *A = J[i][k], *B = J[k + 1][l], *C = J[l + 1][j];
+                    const cplx ac = cdot(A, C), ab = cdot(A, B), bc = cdot(B, C);
+                    for (int mu = 0; mu < 4; ++mu) acc[mu] += (g * g / Q2) * (2 * ac * B[mu] - ab * C[mu] - bc * A[mu]);
+                }
+            for (int mu = 0; mu < 4; ++mu) J[i][j][mu] = acc[mu];
+        }
+    cplx U[MAXG + 1][2][4];
+    memcpy(U[0][0], X->row, sizeof(cplx) * 4);
+    cplx amp = 0;
+    for (int m = 0; m <= n; ++m)
+        for (int e = 0; e < 2; ++e) {
+            if (m == 0 && e == 0) continue;
+            cplx acc[4] = {0, 0, 0, 0};
+            for (int l = 0; l < m; ++l) {
+                cplx js[4][4], t[4];
+                slash_c(J[l][m - 1], js);
+                row_mat(U[l][e], js, t);
+                for (int a = 0; a < 4; ++a) acc[a] += CI * g * t[a];
+            }
+            if (e == 1) {
+                cplx t[4];
+                row_mat(U[m][0], (cplx(*)[4])X->GE, t);
+                for (int a = 0; a < 4; ++a) acc[a] += t[a];
+            }
+            if (m == n && e == 1) {
+                amp = row_col(acc, X->col);
+                break;
+            }
+            real P[4];
+            for (int mu = 0; mu < 4; ++mu) P[mu] = X->prow[mu] - (m > 0 ? Q[0][m - 1][mu] : 0) - e * X->qE[mu];
+            cplx S[4][4];
+            fprop(P, 0, 0, S);
+            row_mat(acc, S, U[m][e]);
+        }
+    return amp;
+}
+
+static void qew_ordered(const qew_ext *X, cplx *out) {
+    int sigma[MAXG];
+    for (int i = 0; i < X->n; ++i) sigma[i] = i;
+    int k = 0;
+    do {
+        out[k++] = qew_amp(X, sigma);
+    } while (next_perm(sigma, X->n));
+}
+
+/* |M|^2 per event: norm x sum over helicities of J^dagger C J, C the colour
+ * matrix of the quark line with n gluons ([n!][n!]). */
+int oracle_qew(const double *mom, int64_t nevt, const int *desc, const double *cpl, const double *colour,
+               double norm, double *out, double *qhel) {
+    if (!mom || !desc || !cpl || !colour || !out || nevt < 0) return -1;
+    const int n = desc[0], np = desc[1];
+    if (n < 0 || n > MAXG - 1 || np > MAXNP) return -1;
+    const int ncol = factorial(n), nh = 1 << np;
+    real *C = (real *)malloc(sizeof(real) * ncol * ncol);
+    for (int i = 0; i < ncol * ncol; ++i) C[i] = colour[i];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ev = 0; ev < nevt; ++ev) {
+        real m[4 * MAXNP];
+        for (int j = 0; j < 4 * np; ++j) m[j] = mom[4 * np * ev + j];
+        cplx J[120];
+        real total = 0;
+        for (int h = 0; h < nh; ++h) {
+            qew_ext X;
+            qew_setup(m, desc, cpl, h, -1, 0, &X);
+            qew_ordered(&X, J);
+            const real qh = colour_form(J, C, ncol);
+            if (qhel) qhel[(int64_t)nh * ev + h] = (double)qh;
+            total += qh;
+        }
+        out[ev] = (double)(total * norm);
+    }
+    free(C);
+    return 0;
+}
+
+/* Partial amplitudes (n! of them, lexicographic orders) of one event at one
+ * helicity; gauge_gluon >= 0 replaces that gluon's polarisation by q/q^0,
+ * gauge_ew replaces the insertion's vectors by its momentum.  out: [n!][2]. */
+int oracle_qew_amps(const double *mom1, const int *desc, const double *cpl, int h, int gauge_gluon, int gauge_ew,
+                    double *out) {
+    if (!mom1 || !desc || !cpl || !out) return -1;
+    const int n = desc[0], np = desc[1];
+    if (n < 0 || n > MAXG - 1 || np > MAXNP) return -1;
+    real m[4 * MAXNP];
+    for (int j = 0; j < 4 * np; ++j) m[j] = mom1[j];
+    qew_ext X;
+    qew_setup(m, desc, cpl, h, gauge_gluon, gauge_ew, &X);
+    cplx J[120];
+    qew_ordered(&X, J);
+    for (int k = 0; k < factorial(n); ++k) {
+        out[2 * k] = (double)CREAL(J[k]);
+        out[2 * k + 1] = (double)CIMAG(J[k]);
+    }
+    return 0;
+}
+
+/* The external pieces of one event at one helicity, for checks against the
+ * gluon recursion: gluon q and eps, the row spinor and its momentum, the
+ * column spinor, the insertion's momentum and its vector (for a vector-like
+ * quark coupling, EL = ER).  out (doubles): q[n][4], eps[n][4][2],
+ * prow[4], row[4][2], col[4][2], qE[4], EL[4][2], ER[4][2]. */
+static void qew_vectors(const real *mom, const int *d, const double *cpl, int h, cplx EL[4], cplx ER[4]) {
+    /* recompute the insertion vectors (the setup keeps only their matrix) */
+    const real *pm = mom + 4 * d[6], *pp = mom + 4 * d[7];
+    const int np = d[1];
+    const int lm = ((h >> (np - 1 - d[6])) & 1) ? 1 : -1, lp = ((h >> (np - 1 - d[7])) & 1) ? 1 : -1;
+    cplx um[4], ubm[4], vp[4];
+    u_spinor(pm, 0, lm, um);
+    bar(um, ubm);
+    v_spinor(pp, 0, lp, vp);
+    const real e = cpl[0], sw2 = cpl[1], mz = cpl[2], wz = cpl[3];
+    const real Qq = cpl[5], T3q = cpl[6], Ql = cpl[7], T3l = cpl[8];
+    const real gz = e / RSQRT(sw2 * (1 - sw2));
+    const real gLq = T3q - Qq * sw2, gRq = -Qq * sw2, gLl = T3l - Ql * sw2, gRl = -Ql * sw2;
+    real k[4];
+    for (int mu = 0; mu < 4; ++mu) k[mu] = pm[mu] + pp[mu];
+    const real k2 = rdot(k, k);
+    const cplx dz = (k2 - mz * mz) + CI * (mz * wz);
+    for (int mu = 0; mu < 4; ++mu) {
+        cplx t[4], tl[4], tr[4];
+        row_mat(ubm, G[mu], t);
+        const cplx jg = row_col(t, vp);
+        cplx PL[4][4], PR[4][4], GL[4][4], GR[4][4];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                PL[i][j] = ((i == j ? 1 : 0) - G5[i][j]) / 2;
+                PR[i][j] = ((i == j ? 1 : 0) + G5[i][j]) / 2;
+            }
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                cplx a = 0, b = 0;
+                for (int l = 0; l < 4; ++l) {
+                    a += G[mu][i][l] * PL[l][j];
+                    b += G[mu][i][l] * PR[l][j];
+                }
+                GL[i][j] = a;
+                GR[i][j] = b;
+            }
+        row_mat(ubm, GL, tl);
+        row_mat(ubm, GR, tr);
+        const cplx jz = gLl * row_col(tl, vp) + gRl * row_col(tr, vp);
+        const cplx ga = CI * e * e * Qq * Ql * jg / k2;
+        EL[mu] = ga + CI * gz * gz * gLq * jz / dz;
+        ER[mu] = ga + CI * gz * gz * gRq * jz / dz;
+    }
+}
+
+int oracle_qew_externals(const double *mom1, const int *desc, const double *cpl, int h, double *out) {
+    if (!mom1 || !desc || !cpl || !out) return -1;
+    const int n = desc[0], np = desc[1];
+    if (n < 0 || n > MAXG - 1 || np > MAXNP) return -1;
+    real m[4 * MAXNP];
+    for (int j = 0; j < 4 * np; ++j) m[j] = mom1[j];
+    qew_ext X;
+    qew_setup(m, desc, cpl, h, -1, 0, &X);
+    cplx EL[4], ER[4];
+    qew_vectors(m, desc, cpl, h, EL, ER);
+    double *o = out;
+    for (int a = 0; a < n; ++a)
+        for (int mu = 0; mu < 4; ++mu) *o++ = (double)X.q[a][mu];
+    for (int a = 0; a < n; ++a)
+        for (int mu = 0; mu < 4; ++mu) {
+            *o++ = (double)CREAL(X.eps[a][mu]);
+            *o++ = (double)CIMAG(X.eps[a][mu]);
+        }
+    for (int mu = 0; mu < 4; ++mu) *o++ = (double)X.prow[mu];
+    for (int i = 0; i < 4; ++i) {
+        *o++ = (double)CREAL(X.row[i]);
+        *o++ = (double)CIMAG(X.row[i]);
+    }
+    for (int i = 0; i < 4; ++i) {
+        *o++ = (double)CREAL(X.col[i]);
+        *o++ = (double)CIMAG(X.col[i]);
+    }
+    for (int mu = 0; mu < 4; ++mu) *o++ = (double)X.qE[mu];
+    for (int mu = 0; mu < 4; ++mu) {
+        *o++ = (double)CREAL(EL[mu]);
+        *o++ = (double)CIMAG(EL[mu]);
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        *o++ = (double)CREAL(ER[mu]);
+        *o++ = (double)CIMAG(ER[mu]);
+    }
+    return 0;
+}
+
+/* Route 2's colour-ordered amplitude for explicit externals: n gluon-like
+ * legs (incoming-flow momenta q[n][4], vectors eps[n][4][2]), row spinor and
+ * its momentum, column spinor, line mass and width, coupling g; one order. */
+int oracle_bg_custom(int n, const double *q, const double *eps, const double *prow, const double *row,
+                     const double *col, double m, double w, double g, const int *sigma, int with4, double *out) {
+    if (n < 1 || n > MAXG || !q || !eps || !prow || !row || !col || !sigma || !out) return -1;
+    ggx_ext X;
+    X.n = n;
+    X.mt = m;
+    X.wt = w;
+    X.gs = g;
+    for (int a = 0; a < n; ++a)
+        for (int mu = 0; mu < 4; ++mu) {
+            X.q[a][mu] = q[4 * a + mu];
+            X.eps[a][mu] = eps[8 * a + 2 * mu] + CI * eps[8 * a + 2 * mu + 1];
+        }
+    for (int mu = 0; mu < 4; ++mu) {
+        X.p3[mu] = prow[mu];
+        X.ubar3[mu] = row[2 * mu] + CI * row[2 * mu + 1];
+        X.v4[mu] = col[2 * mu] + CI * col[2 * mu + 1];
+    }
+    cplx a;
+    bg_amp(&X, sigma, &a, with4);
+    out[0] = (double)CREAL(a);
+    out[1] = (double)CIMAG(a);
     return 0;
 }
