@@ -110,7 +110,7 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8, tol=None):
     m.close()
     achieved = info["flops_per_event"] * nevt / k_s / 1e12
     kernel = {"gg_ttggg": f"k_me_gg_coop<proc_{proc}>", "ee_mumu": "k_me_ee<proc_ee_mumu>"}.get(
-        proc, f"k_me_gg<proc_{proc}>")
+        proc, f"k_me_qew<proc_{proc}>" if proc.startswith("gux_") else f"k_me_gg<proc_{proc}>")
     return {"workload": f"{proc}, {nevt} RAMBO points seed {seed}", "MEs_per_s": nevt / wall, "kernel": kernel,
             "traffic": traffic_from_profile(proc, kernel),
             "kernel_ms": k_s * 1e3, "flops_per_event": info["flops_per_event"],
@@ -522,8 +522,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
     ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,configs,sweep,ps,colour,mc",
+    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,dy3j,configs,sweep,ps,colour,mc",
                     help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3); "
+                         "dy3j: g ubar -> tau+ tau- g g ubar, the DY+3j subprocess (2^20 points, seed 4); "
                          "configs: e+e- -> mu+mu- (16384 points, seed 0) and g g -> t tbar (2^20, seed 1); "
                          "sweep: events per launch 2^10..2^20 at 1, 4, 16, 64 lanes per event; "
                          "ps: the GPU phase-space sampler on the benchmark's workload; "
@@ -620,6 +621,11 @@ def main():
         line["processes"]["gg_ttggg"] = bench_process(me, "gg_ttggg", 1 << 18, 3, max(2, args.steps // 5), stream,
                                                       tol=args.tol if "mixed" in forms else None)
         log(f"gg_ttggg: {line['processes']['gg_ttggg']}")
+    if "dy3j" in forms:
+        # the paper's DY+3j subprocess (Sec. 3), a quark line + lepton pair
+        line["processes"]["gux_taptamggux"] = bench_process(me, "gux_taptamggux", 1 << 20, 4, args.steps, stream,
+                                                            check=64)
+        log(f"dy3j: {line['processes']['gux_taptamggux']['MEs_per_s']:.3e} MEs/s")
     if "configs" in forms:
         line["processes"]["ee_mumu"] = bench_process(me, "ee_mumu", 16384, 0, args.steps, stream, check=64)
         line["processes"]["gg_tt"] = bench_process(me, "gg_tt", 1 << 20, 1, args.steps, stream, check=64)

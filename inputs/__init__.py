@@ -142,6 +142,11 @@ PROCESS_KINEMATICS = {
     "gg_ttg": dict(roots=13000.0, masses=(MT, MT, 0.0)),
     "gg_ttgg": dict(roots=13000.0, masses=(MT, MT, 0.0, 0.0)),
     "gg_ttggg": dict(roots=13000.0, masses=(MT, MT, 0.0, 0.0, 0.0)),
+    # quark line + lepton pair (particles g, ubar, tau+, tau-, then gluons, ubar),
+    # all massless; the gluon cuts apply to every final-state parton
+    "gux_taptamux": dict(roots=13000.0, masses=(0.0, 0.0, 0.0)),
+    "gux_taptamgux": dict(roots=13000.0, masses=(0.0, 0.0, 0.0, 0.0)),
+    "gux_taptamggux": dict(roots=13000.0, masses=(0.0, 0.0, 0.0, 0.0, 0.0)),
 }
 
 

@@ -17,7 +17,8 @@ GEN = os.path.join(CSRC, "gen")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libme.so")
 
-PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"]
+PROCESSES = ["ee_mumu", "gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg", "gux_taptamux", "gux_taptamgux",
+             "gux_taptamggux"]
 
 # processes whose colour-flow amplitudes live in LDS (workgroup kernel of me_coop.h)
 COOP = {"gg_ttggg"}
@@ -40,6 +41,34 @@ HIPFLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", CSRC,
 ]
+
+_TU_QEW = """// Generated translation unit: kernels of {name} (quark line + lepton pair).
+#include "me_qew.h"
+{include}
+
+static hipError_t launch_f64(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                             const me_params& prm, double* qhel, int lg, hipStream_t s) {{
+    const dim3 grid((unsigned)(((nevt << lg) + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL((k_me_qew<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm, qhel,
+                       nullptr, nullptr, lg);
+    return hipGetLastError();
+}}
+
+static hipError_t launch_f64_idx(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
+                                 const me_params& prm, const int* idx, const int* count, hipStream_t s) {{
+    const dim3 grid((unsigned)((nevt + ME_BLOCK - 1) / ME_BLOCK));
+    hipLaunchKernelGGL((k_me_qew<{proc}>), grid, dim3(ME_BLOCK), 0, s, mom, nevt, out, hels, nh, prm,
+                       nullptr, idx, count, 0);
+    return hipGetLastError();
+}}
+
+#ifndef __HIP_DEVICE_COMPILE__  // the table entry holds host function pointers
+extern const me_process_desc me_desc_{name} = {{
+    "{name}", ME_KIND_QEW, {proc}::npart, {proc}::ndiag, {proc}::ncol, {proc}::nhel,
+    {proc}::flops_amp, {proc}::flops_colour, {proc}::flops_executed, launch_f64, launch_f64_idx, nullptr, 8.0,
+    0.0, nullptr, nullptr, 0, nullptr}};
+#endif
+"""
 
 _TU = """// Generated translation unit: kernels of {name}.
 #include "me_mixed.h"
@@ -205,11 +234,16 @@ def _write(path, text):
 
 def generate_sources(processes):
     sys.path.insert(0, os.path.dirname(HERE))
-    from paper_2503_21935_amd.gen import MULTICHANNEL, generate
+    from paper_2503_21935_amd.gen import MULTICHANNEL, QEW_SPECS, generate
 
-    info = generate(GEN, [p for p in processes if p.startswith("gg_")])
+    info = generate(GEN, [p for p in processes if p.startswith("gg_") or p in QEW_SPECS])
     tus = []
     for name in processes:
+        if name in QEW_SPECS:
+            path = os.path.join(GEN, f"tu_{name}.hip")
+            _write(path, _TU_QEW.format(name=name, include=f'#include "gen/proc_{name}.h"', proc=f"proc_{name}"))
+            tus.append(path)
+            continue
         if name == "ee_mumu":
             inc, kernel, proc, kind = "", "k_me_ee", "proc_ee_mumu", "ME_KIND_EE"
             mixed, mixed_ptr, colerr = "", "nullptr", "0.0"

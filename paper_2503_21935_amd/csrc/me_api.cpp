@@ -143,9 +143,9 @@ static int helicity_filter(me_ctx* c) {
     double roots = 13000.0;
     if (pd->kind == ME_KIND_EE) {
         roots = 500.0;
-    } else {
+    } else if (pd->kind == ME_KIND_GG) {
         fm[0] = fm[1] = c->prm.mt;
-    }
+    }  // quark-line + lepton-pair processes: every final state massless
     std::vector<double> pts;
     probe_points(pd, roots, fm.data(), npts, pts);
     double *d_mom = nullptr, *d_out = nullptr, *d_q = nullptr;
@@ -208,6 +208,7 @@ int me_init(const char* process, const double* couplings, int n_couplings, const
     c->prm.gr = sw2;
     c->prm.mz = mz;
     c->prm.wz = wz;
+    c->prm.sw2 = sw2;
     c->d_good = nullptr;
     c->d_all = nullptr;
     c->mode = ME_FP64;

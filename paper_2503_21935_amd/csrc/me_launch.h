@@ -28,7 +28,7 @@ typedef hipError_t (*me_launch_mixed_fn)(const double* mom, int64_t nevt, double
 typedef hipError_t (*me_launch_mc_fn)(const double* mom, int64_t nevt, double* out, const int* hels, int nh,
                                       const me_params& prm, const int* chan, double* alpha, hipStream_t stream);
 
-enum { ME_KIND_EE = 0, ME_KIND_GG = 1 };
+enum { ME_KIND_EE = 0, ME_KIND_GG = 1, ME_KIND_QEW = 2 };
 
 struct me_process_desc {
     const char* name;

@@ -9,6 +9,7 @@ struct me_params {
     double e;               // electromagnetic coupling sqrt(4 pi alpha)
     double gz, gl, gr;      // Z coupling e/(sw cw) and chiral charges of charged leptons
     double mz, wz;          // Z mass and width
+    double sw2;             // sin^2 theta_W
 };
 
 // Device-side access to a process's colour-matrix numerators (specialised by
@@ -39,6 +40,15 @@ struct gg_ext {
     lds_cdouble* Q;   // this lane's column of the tile's momenta
     double m, mw, g;  // top mass, mass * width, strong coupling
     T mT, gT;         // the same in the amplitude type
+};
+
+// External state of a massless quark line with gluons and a photon/Z
+// insertion (the quark-line + lepton-pair processes): the row and column
+// spinors sit in ubar3 and v4, and the insertion gamma^mu (EL_mu P_L + ER_mu
+// P_R) carries the boson propagators, couplings and the lepton current.
+template <typename T, int NG>
+struct qew_ext : gg_ext<T, NG> {
+    vec4<T> EL, ER;
 };
 
 // Momentum of slot j, read from LDS through an address the compiler cannot

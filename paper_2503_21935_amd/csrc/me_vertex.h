@@ -245,6 +245,39 @@ MEV spinor<T> row_slash(const spinor<T>& f, const vec4<T>& W) {
     return o;
 }
 
+// row * (gamma.EL P_L + gamma.ER P_R): a vector insertion with different
+// left- and right-handed couplings (P_L keeps the first two components of the
+// column it acts on), as row_slash with EL in the first half of the result
+// and ER in the second.
+template <typename T>
+MEV spinor<T> row_ew(const spinor<T>& f, const vec4<T>& EL, const vec4<T>& ER) {
+    const cx<T> a = EL.v[0] + EL.v[3], b = EL.v[0] - EL.v[3];
+    const cx<T> c = EL.v[1] + times_i(EL.v[2]), d = EL.v[1] - times_i(EL.v[2]);
+    const cx<T> A = ER.v[0] + ER.v[3], B = ER.v[0] - ER.v[3];
+    const cx<T> C = ER.v[1] + times_i(ER.v[2]), D = ER.v[1] - times_i(ER.v[2]);
+    spinor<T> o;
+    o.s[0] = cfma(f.s[2], a, f.s[3] * c);
+    o.s[1] = cfma(f.s[2], d, f.s[3] * b);
+    o.s[2] = cfma(f.s[0], B, -(f.s[1] * C));
+    o.s[3] = cfma(f.s[1], A, -(f.s[0] * D));
+    return o;
+}
+
+// (gamma.EL P_L + gamma.ER P_R) * column
+template <typename T>
+MEV spinor<T> ew_col(const vec4<T>& EL, const vec4<T>& ER, const spinor<T>& p) {
+    const cx<T> a = EL.v[0] + EL.v[3], b = EL.v[0] - EL.v[3];
+    const cx<T> c = EL.v[1] + times_i(EL.v[2]), d = EL.v[1] - times_i(EL.v[2]);
+    const cx<T> A = ER.v[0] + ER.v[3], B = ER.v[0] - ER.v[3];
+    const cx<T> C = ER.v[1] + times_i(ER.v[2]), D = ER.v[1] - times_i(ER.v[2]);
+    spinor<T> o;
+    o.s[0] = cfma(B, p.s[2], -(D * p.s[3]));
+    o.s[1] = cfma(A, p.s[3], -(C * p.s[2]));
+    o.s[2] = cfma(a, p.s[0], d * p.s[1]);
+    o.s[3] = cfma(c, p.s[0], b * p.s[1]);
+    return o;
+}
+
 // (gamma.W) * column
 template <typename T>
 MEV spinor<T> slash_col(const vec4<T>& W, const spinor<T>& p) {

@@ -10,6 +10,7 @@ import os
 
 from .coop import GGCoopEmitter
 from .emit import GGEmitter
+from .qew import QEWEmitter
 
 GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # Maximum number of wavefunctions kept alive at once by the emitted program
@@ -29,10 +30,40 @@ COOP_WINDOW = {"gg_ttggg": 16}
 # Processes that also get the multi-channel program (single-diagram weights).
 MULTICHANNEL = {"gg_tt", "gg_ttg", "gg_ttgg"}
 
+# Quark-line + lepton-pair processes: n gluons, particle count, the quark
+# line's row end (particle, 1 if an incoming antiquark vbar(p), 0 if an
+# outgoing quark ubar(p)) and column end (particle, 1 if an incoming quark
+# u(p), 0 if an outgoing antiquark v(p)), the l- and l+ particles, the gluons
+# (particle, incoming), (charge, T3) of the quark and of the lepton, and the
+# average over spins, colours and identical final states.  The momenta come
+# in this particle order.
+_UP, _TAU = (2.0 / 3.0, 0.5), (-1.0, -0.5)
+QEW_SPECS = {
+    "gux_taptamggux": dict(n=3, npart=7, row=(1, 1), col=(6, 0), lm=3, lp=2, gluons=((0, 1), (4, 0), (5, 0)),
+                           quark=_UP, lepton=_TAU, avg=4 * 24 * 2, title="g ubar -> tau+ tau- g g ubar"),
+    "gux_taptamgux": dict(n=2, npart=6, row=(1, 1), col=(5, 0), lm=3, lp=2, gluons=((0, 1), (4, 0)),
+                          quark=_UP, lepton=_TAU, avg=4 * 24, title="g ubar -> tau+ tau- g ubar"),
+    "gux_taptamux": dict(n=1, npart=5, row=(1, 1), col=(4, 0), lm=3, lp=2, gluons=((0, 1),),
+                         quark=_UP, lepton=_TAU, avg=4 * 24, title="g ubar -> tau+ tau- ubar"),
+}
+# live-set caps of the quark-line programs (small: every program fits)
+QEW_CAP = {"gux_taptamggux": 14, "gux_taptamgux": 12, "gux_taptamux": 12}
+
 
 def generate(outdir: str, processes=None, merge: bool = True) -> dict:
     os.makedirs(outdir, exist_ok=True)
     info = {}
+    for name, spec in QEW_SPECS.items():
+        if processes and name not in processes:
+            continue
+        em = QEWEmitter(name, spec, merge=merge, cap=QEW_CAP[name])
+        src = em.render()
+        path = os.path.join(outdir, f"proc_{name}.h")
+        old = open(path).read() if os.path.exists(path) else None
+        if old != src:
+            with open(path, "w") as f:
+                f.write(src)
+        info[name] = dict(em.plan.stats(), lcd=em.lcd, ncol=len(em.perms))
     for name, n in GG_PROCESSES.items():
         if processes and name not in processes:
             continue

@@ -74,15 +74,24 @@ def _clean(c):
 
 
 class Plan:
-    """Currents, fermion-line nodes and amplitudes for n gluons."""
+    """Currents, fermion-line nodes and amplitudes for n gluons.
 
-    def __init__(self, n: int, merge: bool):
+    With ``ew=True`` the fermion line also carries one colourless insertion
+    (a photon/Z current from a lepton pair), block ``self.ew``, placed at every
+    point of every block sequence; all gluons may then meet in one tree (the
+    full-set currents are ordinary blocks)."""
+
+    def __init__(self, n: int, merge: bool, ew: bool = False):
         self.n = n
         self.merge = merge
+        self.ew_mode = ew
         self.currents: list[Current] = []
         self.by_set: dict[frozenset, list[int]] = {}
         self.root_groups: list[dict] = []  # full-set vertex sums, contracted with V_T
         self._build_currents()
+        self.ew = None
+        if ew:
+            self.ew = self._new(leaves=frozenset(["E"]), colour={(): 1}, is_leaf=True).id
         self.L: dict[tuple, int] = {(): 0}   # block-id tuple -> node id (0 = ubar)
         self.R: dict[tuple, int] = {(): 0}   # (0 = v)
         self.L_order: list[tuple] = []
@@ -140,7 +149,7 @@ class Plan:
             for S in itertools.combinations(range(n), size):
                 S = frozenset(S)
                 groups = self._group(S, self._candidates(S))
-                if size < n:
+                if size < n or self.ew_mode:
                     ids = []
                     for g in groups:
                         c = self._new(leaves=S, colour=g["colour"], terms=g["terms"])
@@ -152,10 +161,14 @@ class Plan:
     # -- fermion line and amplitudes -------------------------------------------
     def _block_sequences(self):
         for part in D._ordered_partitions(range(self.n)):
-            if len(part) < 2:
+            if len(part) < 2 and not self.ew_mode:
                 continue
             for combo in itertools.product(*(self.by_set[B] for B in part)):
-                yield combo
+                if self.ew_mode:
+                    for pos in range(len(combo) + 1):
+                        yield combo[:pos] + (self.ew,) + combo[pos:]
+                else:
+                    yield combo
 
     def _need(self, table, key):
         """Number of new nodes needed to obtain table[key] (prefix/suffix closure)."""

@@ -74,6 +74,34 @@ def test_plan_covers_every_diagram(n):
     assert p.stats()["colour_pairs"] == want
 
 
+@pytest.mark.parametrize("n,diagrams,amplitudes", [(1, 2, 2), (2, 8, 8), (3, 50, 54)])
+def test_quark_line_with_insertion_plan(n, diagrams, amplitudes):
+    """Quark line + photon/Z insertion: every ordered partition of the gluons
+    into trees (1, 1, 4 trees over 1, 2, 3 gluons, four-gluon vertices once)
+    with the insertion at each of the k + 1 points of k blocks; the unmerged
+    plan has one amplitude per diagram and four-gluon colour channel, and the
+    merged plan carries the same colour-flow sums."""
+    from paper_2503_21935_amd.gen import QEW_SPECS
+    from paper_2503_21935_amd.gen.plan import Plan
+    from paper_2503_21935_amd.gen.qew import QEWEmitter
+
+    name = {1: "gux_taptamux", 2: "gux_taptamgux", 3: "gux_taptamggux"}[n]
+    em = QEWEmitter(name, QEW_SPECS[name])
+    assert em.feynman_diagrams() == diagrams
+    unmerged, merged = Plan(n, merge=False, ew=True), Plan(n, merge=True, ew=True)
+    assert len(unmerged.amps) == amplitudes
+    assert all(a["kind"] == "ffv" for a in merged.amps)
+
+    def flows(p):
+        tot = {}
+        for a in p.amps:
+            for k, v in a["colour"].items():
+                tot[k] = tot.get(k, 0) + abs(v)
+        return tot
+
+    assert set(flows(unmerged)) == set(flows(merged))
+
+
 @pytest.mark.parametrize("n", [3, 4])
 def test_merged_plan_colour_is_consistent(n):
     """Merged plan: summing the per-diagram colour expansions of each merged
