@@ -374,7 +374,6 @@ def unweighting_scan(me, ctx, net, mu_t, wu_t, uu_t, nu, mu, sig, s_c, wex_c, me
 
 
 def bench_surrogate(me, args, stream):
-    import numpy as np
     import torch
 
     from inputs import gluon_cuts, process_points, uniforms
@@ -398,15 +397,17 @@ def bench_surrogate(me, args, stream):
     n_val = n // 10
     n_fit = (n - n_val) // args.batch * args.batch
     net = me.Surrogate(seed=1004)
-    rng = np.random.default_rng(7)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     steps_per_epoch = n_fit // args.batch
     total = steps_per_epoch * args.epochs
     torch.cuda.synchronize()
     tt0 = time.perf_counter()
     step = 0
+    gperm = torch.Generator(device=dev)
+    gperm.manual_seed(7)
     for ep in range(args.epochs):
-        perm = torch.from_numpy(rng.permutation(n_fit).astype(np.int32) + n_val).to(dev)
+        # the epoch's sample order, drawn on the device
+        perm = (torch.randperm(n_fit, generator=gperm, device=dev) + n_val).to(torch.int32)
         # the epoch's steps in one call (one cooperative launch), cosine rates
         lrs = [0.5 * args.lr * (1 + math.cos(math.pi * (step + b) / total)) for b in range(steps_per_epoch)]
         net.train_steps(x, t, perm, args.batch, torch.tensor(lrs, dtype=torch.float32, device=dev), None, stream)

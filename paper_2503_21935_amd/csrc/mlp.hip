@@ -408,26 +408,27 @@ __global__ void k_to_bf16_t(const float* __restrict__ theta, int64_t o, int rows
 }
 
 // ---------------------------------------------------------------------------
-// Fused training step for width 256 (one cooperative launch, two grid-wide
-// barriers).  The batch's rows are independent through the whole forward and
-// backward chain, so phase 1 gives each block tiles of FT_R rows and carries
-// them through every layer forward (activations and pre-activations in LDS),
-// the output layer and loss, and every layer backward down to the first
-// pre-activation gradient, reading the BF16 weights (and their transposes)
-// from L2 with all of a layer's loads issued before its first MFMA.  Each
-// tile's activations and gradients also go to global memory transposed
-// ([feature][batch], 32-byte runs per feature written from LDS), and its
-// share of the output layer's gradient to a per-tile partial.  The only
-// cross-row work is the weight and bias gradients, sums over the batch: after
-// the first barrier, phase 2 computes them as GEMMs dW_l = dZ_l^T H_{l-1} on
-// 64 x 64 output tiles, each over a quarter of the batch (partial slabs in a
-// fixed layout), and adds the output layer's per-tile partials per quarter.
-// After the second barrier, phase 3 adds the slabs in a fixed order (the
-// result does not depend on the grid) and applies Adam to the FP32 masters,
-// refreshing the BF16 copies.  Rounding points are those of the layered path.
+// Fused training step for width 256 (one cooperative launch; one grid-wide
+// barrier inside a step, one between steps).  The batch's rows are
+// independent through the whole forward and backward chain, so phase 1 gives
+// each block tiles of FT_R rows and carries them through every layer forward
+// (activations and pre-activations in LDS), the output layer and loss, and
+// every layer backward down to the first pre-activation gradient, reading the
+// BF16 weights (and their transposes) in MFMA fragment order from L2, each
+// layer's fragments loaded during the previous layer's epilogue.  Each tile's
+// activations and gradients also go to global memory transposed
+// ([feature][batch], fragment order, written from LDS), and its share of the
+// output layer's gradient to a per-tile partial.  The only cross-row work is
+// the weight and bias gradients, sums over the batch: after the barrier,
+// phase 2 computes them as GEMMs dW_l = dZ_l^T H_{l-1} on 32 x 32 tiles, one
+// per block, each wave over a quarter of the batch; the quarters are added in
+// LDS in a fixed order (the result does not depend on the grid) and the block
+// applies Adam to the tile's FP32 masters and refreshes their BF16 copies, so
+// every parameter is updated by the block that formed its gradient.  Rounding
+// points are those of the layered path.
 // ---------------------------------------------------------------------------
 #define FT_R 16        // rows per phase-1 tile
-#define FT_S 4         // batch splits of the weight gradients
+#define FT_S 4         // batch quarters of the weight-gradient sums, one per wave
 #define FT_MAXDEPTH 4  // pre-activations of every layer stay in LDS
 
 struct ft_args {
@@ -449,7 +450,6 @@ struct ft_args {
     bf16* HT[FT_MAXDEPTH];    // [256][M], the same
     bf16* DZT[FT_MAXDEPTH];   // [256][M], the same
     float* opart;             // [257][M / FT_R]: output-layer gradient per tile (weights, then bias)
-    float* slab;              // [FT_S][np]
     float* lossp;             // [gridDim.x]
     unsigned* bar;            // grid barrier state (zeroed once at allocation)
     float* loss;              // [nsteps] or nullptr
@@ -528,6 +528,29 @@ __device__ __forceinline__ void ft_store_t(const bf16* S, int c, bf16* dst, int6
     const int q = (int)(m0 & 31) >> 3;  // 0 or 2
     *reinterpret_cast<bf16x8*>(dst + base + 128 * q) = v0;
     *reinterpret_cast<bf16x8*>(dst + base + 128 * (q + 1)) = v1;
+}
+
+// Adam on parameter i (FP32 master, moments) with gradient g and the loaded
+// old values; returns the new master value.
+__device__ __forceinline__ float ft_adam(const ft_args& a, int64_t i, float g, float mo, float vo, float th, float lr,
+                                         float c1, float c2) {
+    const float mi = 0.9f * mo + 0.1f * g;
+    const float vi = 0.999f * vo + 0.001f * g * g;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float t2 = th - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+    a.theta[i] = t2;
+    return t2;
+}
+
+// The update of a parameter without BF16 copies (biases, output layer), or
+// its gradient only.
+__device__ __forceinline__ void ft_update(const ft_args& a, int64_t i, float g, float lr, float c1, float c2) {
+    if (a.grad_out) {
+        a.grad_out[i] = g;
+        return;
+    }
+    ft_adam(a, i, g, a.m[i], a.v[i], a.theta[i], lr, c1, c2);
 }
 
 // The 16 input rows (padded to MLP_KPAD features) and targets of the tile at
@@ -692,178 +715,169 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
         }
         ft_grid_sync(a.bar);
 
-        // ---------------- phase 2: batch sums (weight and bias gradients) ----------------
-        if (blockIdx.x == 0 && loss) {
-            if (tid == 0) {
-                float s = 0.f;
-                for (int i = 0; i < (int)gridDim.x; ++i) s += a.lossp[i];
-                loss[0] = s / (float)M;
-            }
+        // ---------------- phase 2: weight gradients and the update ----------------
+        if (blockIdx.x == 0 && loss && tid == 0) {
+            float s = 0.f;
+            for (int i = 0; i < (int)gridDim.x; ++i) s += a.lossp[i];
+            loss[0] = s / (float)M;
         }
-        const int64_t span = M / FT_S;
-        // items: for each split s: per layer l, 4 n-blocks x nkb(l) k-blocks of 64, then four output-layer items
-        int per_split = 4;
-        for (int l = 0; l < a.depth; ++l) per_split += 4 * ((a.L.fan_in[l] + 63) / 64);
-        const int nitems = per_split * FT_S;
+        // the next step's first tile, loaded across this phase and the barrier
+        ft_rows nxt;
+        const bool pre = st + 1 < a.nsteps && (int)blockIdx.x < nrt;
+        if (pre) ft_rows_load(a, st + 1, (int64_t)blockIdx.x * FT_R, tid, nxt);
+        // items: per layer l, 8 x (padded fan-in / 32) tiles of 32 x 32 of dW_l
+        // (n-tile major), then eight output-layer items
+        int nw = 0;
+        for (int l = 0; l < a.depth; ++l) nw += 8 * (((l == 0) ? MLP_KPAD : W) / 32);
+        const int nitems = nw + 8;
+        float* part = &Zs[0][0][0];  // [wave][32][32] partial tiles, then [wave][32] bias partials
         // Items that share operand rows are neighbours in this order; blocks go
         // round-robin over the 8 XCDs, so slot v of XCD x takes item x q + v:
         // each XCD's L2 then fetches about an eighth of the operands instead
         // of nearly all of them.
-        const int q = (nitems + 7) / 8;
-        for (int vb = blockIdx.x; vb < 8 * q; vb += gridDim.x) {
-            const int it = (vb % 8) * q + vb / 8;
+        const int q8 = (nitems + 7) / 8;
+        for (int vb = blockIdx.x; vb < 8 * q8; vb += gridDim.x) {
+            const int it = (vb % 8) * q8 + vb / 8;
             if (it >= nitems) continue;
-            const int s = it / per_split;
-            int j = it % per_split;
-            const int64_t mb = (int64_t)s * span;
-            float* slab = a.slab + (int64_t)s * a.np;
-            if (j >= per_split - 4) {
-                // output layer, columns 64 oq .. 64 oq + 63 (the last item also takes
-                // the bias): four threads per column add this quarter's per-tile
-                // partials in a fixed interleave, then combine by shuffles
-                const int oq = j - (per_split - 4), tpq = nrt / FT_S;
-                const int c = 64 * oq + (tid >> 2), q = tid & 3;
-                const float* src = a.opart + (int64_t)c * nrt + (int64_t)s * tpq;
-                float acc = 0.f;
-#pragma unroll 16
-                for (int i = q; i < tpq; i += 4) acc += src[i];
-                acc += __shfl_xor(acc, 1);
-                acc += __shfl_xor(acc, 2);
-                if (q == 0) slab[a.wout_off + c] = acc;
-                if (oq == 3 && wave == 0) {
-                    const float* sb = a.opart + (int64_t)W * nrt + (int64_t)s * tpq;
+            if (it >= nw) {
+                // output layer, columns 32 oq .. 32 oq + 31 (the last item also takes
+                // the bias): eight threads per column add the per-tile partials in a
+                // fixed interleave, combine them by shuffles and update
+                const int oq = it - nw;
+                const int c = 32 * oq + (tid >> 3), q = tid & 7;
+                const float* src = a.opart + (int64_t)c * nrt;
+                float g = 0.f;
+#pragma unroll 8
+                for (int i = q; i < nrt; i += 8) g += src[i];
+                g += __shfl_xor(g, 1);
+                g += __shfl_xor(g, 2);
+                g += __shfl_xor(g, 4);
+                if (q == 0) ft_update(a, a.wout_off + c, g, lr, c1, c2);
+                if (oq == 7 && wave == 0) {
+                    const float* sb = a.opart + (int64_t)W * nrt;
                     float d = 0.f;
-#pragma unroll 16
-                    for (int i = lane & 3; i < tpq; i += 4) d += sb[i];
+#pragma unroll 8
+                    for (int i = lane & 7; i < nrt; i += 8) d += sb[i];
                     d += __shfl_xor(d, 1);
                     d += __shfl_xor(d, 2);
-                    if (lane == 0) slab[a.bout_off] = d;
+                    d += __shfl_xor(d, 4);
+                    if (lane == 0) ft_update(a, a.bout_off, d, lr, c1, c2);
                 }
                 continue;
             }
-            int l = 0;
+            int l = 0, j = it;
             for (; l < a.depth; ++l) {
-                const int nl = 4 * ((a.L.fan_in[l] + 63) / 64);
+                const int nl = 8 * (((l == 0) ? MLP_KPAD : W) / 32);
                 if (j < nl) break;
                 j -= nl;
             }
-            const int nkb = (a.L.fan_in[l] + 63) / 64;
-            const int nb = j / nkb, kb = j % nkb;
-            const int fi = a.L.fan_in[l];
-            const int kw = (l == 0) ? MLP_KPAD : W;  // rows of the transposed input copy
-            const bf16* A = a.DZT[l];                // [n][m]
-            const bf16* B = (l == 0) ? a.XT : a.HT[l - 1];  // [k][m]
-            const int n0 = 64 * nb + 16 * wave;
-            const int ntile = min(4, (min(kw, 64 * kb + 64) - 64 * kb) / 16);
-            f32x4 acc[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            float bsum = 0.f;
+            const int kt = ((l == 0) ? MLP_KPAD : W) / 32;
+            const int nb = j / kt, kb = j % kt;
+            const int fi = a.L.fan_in[l], ld = (l == 0) ? MLP_KPAD : fi;
             // operands in fragment order: the fragment of 16-row tile f at batch
-            // step m / 32 starts at (f (M / 32) + m / 32) 512; tiles of rows beyond
-            // the input copy (first layer, second tile pair) read a valid tile
-            // instead, and their products are not stored
-            const bf16* Brow[4];
+            // step m / 32 starts at (f (M / 32) + m / 32) 512
+            const bf16* A = a.DZT[l];                       // dZ_l^T [n][m]
+            const bf16* B = (l == 0) ? a.XT : a.HT[l - 1];  // H_{l-1}^T [k][m]
+            const bf16* Ar[2];
+            const bf16* Br[2];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) Brow[t] = B + (int64_t)min(4 * kb + t, kw / 16 - 1) * (M >> 5) * 512 + lane * 8;
-            const bf16* Arow = A + (int64_t)(n0 >> 4) * (M >> 5) * 512 + lane * 8;
-            auto mstep = [&](const bf16x8& av, const bf16x8 (&bv)[4]) {
+            for (int i = 0; i < 2; ++i) {
+                Ar[i] = A + (int64_t)(2 * nb + i) * (M >> 5) * 512 + lane * 8;
+                Br[i] = B + (int64_t)(2 * kb + i) * (M >> 5) * 512 + lane * 8;
+            }
+            f32x4 acc[2][2];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) bsum += (float)av[q];
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[t], acc[t], 0, 0, 0);
+                for (int k = 0; k < 2; ++k) acc[i][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+            float bsum[2] = {0.f, 0.f};
+            auto mstep = [&](const bf16x8 (&av)[2], const bf16x8 (&bv)[2]) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bsum[i] += (float)av[i][q];
+#pragma unroll
+                    for (int k = 0; k < 2; ++k)
+                        acc[i][k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[k], acc[i][k], 0, 0, 0);
+                }
             };
+            // this wave's quarter of the batch
+            const int64_t mq = M / FT_S, mb = (int64_t)wave * mq;
             constexpr int U = 8;  // batch steps whose loads are all in flight together
             int64_t m = mb;
-            for (; m + 32 * U <= mb + span; m += 32 * U) {
-                bf16x8 av[U], bv[U][4];
+            for (; m + 32 * U <= mb + mq; m += 32 * U) {
+                bf16x8 av[U][2], bv[U][2];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    av[u] = *reinterpret_cast<const bf16x8*>(Arow + 16 * (m + 32 * u));
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) bv[u][t] = *reinterpret_cast<const bf16x8*>(Brow[t] + 16 * (m + 32 * u));
-                }
+                    for (int i = 0; i < 2; ++i) {
+                        av[u][i] = *reinterpret_cast<const bf16x8*>(Ar[i] + 16 * (m + 32 * u));
+                        bv[u][i] = *reinterpret_cast<const bf16x8*>(Br[i] + 16 * (m + 32 * u));
+                    }
 #pragma unroll
                 for (int u = 0; u < U; ++u) mstep(av[u], bv[u]);
             }
-            for (; m < mb + span; m += 32) {
-                bf16x8 bv[4];
-                const bf16x8 av = *reinterpret_cast<const bf16x8*>(Arow + 16 * m);
+            for (; m < mb + mq; m += 32) {
+                bf16x8 av[2], bv[2];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) bv[t] = *reinterpret_cast<const bf16x8*>(Brow[t] + 16 * m);
+                for (int i = 0; i < 2; ++i) {
+                    av[i] = *reinterpret_cast<const bf16x8*>(Ar[i] + 16 * m);
+                    bv[i] = *reinterpret_cast<const bf16x8*>(Br[i] + 16 * m);
+                }
                 mstep(av, bv);
             }
+            // the wave's partial tile: element (n, k) = acc[i][k'][v], n = 16 i + 4 lg + v, k = 16 k' + li
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t >= ntile) continue;
-                const int k = 64 * kb + 16 * t + li;
-                if (k >= fi) continue;
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int n = n0 + 4 * lg + v;
-                    slab[a.L.w_off[l] + (int64_t)n * fi + k] = acc[t][v];
-                }
+                for (int k = 0; k < 2; ++k)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) part[(wave * 32 + 16 * i + 4 * lg + v) * 32 + 16 * k + li] = acc[i][k][v];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                bsum[i] += __shfl_xor(bsum[i], 16);
+                bsum[i] += __shfl_xor(bsum[i], 32);
+                if (lg == 0) part[4096 + wave * 32 + 16 * i + li] = bsum[i];
             }
-            if (kb == 0) {
-                bsum += __shfl_xor(bsum, 16);
-                bsum += __shfl_xor(bsum, 32);
-                if (lg == 0) slab[a.L.b_off[l] + n0 + li] = bsum;
-            }
-        }
-        ft_grid_sync(a.bar);
-
-        // ---------------- phase 3: sum the slabs, Adam, BF16 copies ----------------
-        // the next step's first tile, loaded across the Adam pass and the barrier
-        ft_rows nxt;
-        const bool pre = st + 1 < a.nsteps && (int)blockIdx.x < nrt;
-        if (pre) ft_rows_load(a, st + 1, (int64_t)blockIdx.x * FT_R, tid, nxt);
-        // four parameters per thread per pass, every load of a pass issued first
-        const int64_t stride = (int64_t)gridDim.x * 256;
-        for (int64_t i0 = (int64_t)blockIdx.x * 256 + tid; i0 < a.np; i0 += 4 * stride) {
+            __syncthreads();
+            // the four quarters added in wave order, then four of the tile's 1024
+            // weights per thread (every load first)
             float g[4], mo[4], vo[4], th[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t i = i0 + j * stride;
-                g[j] = mo[j] = vo[j] = th[j] = 0.f;
-                if (i < a.np) {
-#pragma unroll
-                    for (int s = 0; s < FT_S; ++s) g[j] += a.slab[(int64_t)s * a.np + i];
-                    if (!a.grad_out) {
-                        mo[j] = a.m[i];
-                        vo[j] = a.v[i];
-                        th[j] = a.theta[i];
-                    }
+            for (int r = 0; r < 4; ++r) {
+                const int e = tid + 256 * r, n = e >> 5, k = e & 31;
+                g[r] = ((part[n * 32 + k] + part[(32 + n) * 32 + k]) + part[(64 + n) * 32 + k]) + part[(96 + n) * 32 + k];
+                mo[r] = vo[r] = th[r] = 0.f;
+                const int64_t i = a.L.w_off[l] + (int64_t)(32 * nb + n) * fi + 32 * kb + k;
+                if (32 * kb + k < fi && !a.grad_out) {
+                    mo[r] = a.m[i];
+                    vo[r] = a.v[i];
+                    th[r] = a.theta[i];
                 }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t i = i0 + j * stride;
-                if (i >= a.np) break;
+            for (int r = 0; r < 4; ++r) {
+                const int e = tid + 256 * r, n = e >> 5, k = e & 31;
+                const int rr = 32 * nb + n, kk = 32 * kb + k;
+                if (kk >= fi) continue;
+                const int64_t i = a.L.w_off[l] + (int64_t)rr * fi + kk;
                 if (a.grad_out) {
-                    a.grad_out[i] = g[j];
+                    a.grad_out[i] = g[r];
                     continue;
                 }
-                const float mi = 0.9f * mo[j] + 0.1f * g[j];
-                const float vi = 0.999f * vo[j] + 0.001f * g[j] * g[j];
-                a.m[i] = mi;
-                a.v[i] = vi;
-                const float t2 = th[j] - lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
-                a.theta[i] = t2;
-                for (int l = 0; l < a.depth; ++l) {
-                    const int64_t o = a.L.w_off[l];
-                    const int fi = a.L.fan_in[l];
-                    if (i >= o && i < o + (int64_t)W * fi) {
-                        const int r = (int)(i - o) / fi, k = (int)(i - o) % fi;
-                        const int ld = (l == 0) ? MLP_KPAD : fi;
-                        a.wbf[l][r * ld + k] = (bf16)t2;
-                        a.wfr[l][frag_off(r, k, ld)] = (bf16)t2;
-                        if (l > 0) {
-                            a.wbft[l][k * W + r] = (bf16)t2;
-                            a.wtfr[l][frag_off(k, r, W)] = (bf16)t2;
-                        }
-                    }
+                const float t2 = ft_adam(a, i, g[r], mo[r], vo[r], th[r], lr, c1, c2);
+                a.wbf[l][rr * ld + kk] = (bf16)t2;
+                a.wfr[l][frag_off(rr, kk, ld)] = (bf16)t2;
+                if (l > 0) {
+                    a.wbft[l][kk * W + rr] = (bf16)t2;
+                    a.wtfr[l][frag_off(kk, rr, W)] = (bf16)t2;
                 }
             }
+            if (kb == 0 && tid < 32) {
+                const float gb = ((part[4096 + tid] + part[4096 + 32 + tid]) + part[4096 + 64 + tid]) + part[4096 + 96 + tid];
+                ft_update(a, a.L.b_off[l] + 32 * nb + tid, gb, lr, c1, c2);
+            }
+            __syncthreads();  // part is rewritten by the next item
         }
         if (pre) ft_rows_store(nxt, tid, Hs, tgs);
         first_in_lds = pre;
@@ -902,7 +916,7 @@ struct me_mlp {
     int fgrid;               // its grid: co-resident blocks
     int64_t fcap;            // batch capacity of its buffers
     bf16 *XT, *HTb, *DZTb;   // transposed input, activations and gradients [feature][batch]
-    float *fslab, *flossp, *fopart;
+    float *flossp, *fopart;
     unsigned* fbar;          // grid barrier state of the fused kernel
     int64_t cap;             // activation capacity (rows)
     bf16* X;
@@ -1260,19 +1274,17 @@ static int ensure_fused(me_mlp* p, int64_t M) {
     f(p->XT);
     f(p->HTb);
     f(p->DZTb);
-    f(p->fslab);
     f(p->flossp);
     f(p->fopart);
     f(p->fbar);
     p->fbar = nullptr;
     p->XT = p->HTb = p->DZTb = nullptr;
-    p->fslab = p->flossp = p->fopart = nullptr;
+    p->flossp = p->fopart = nullptr;
     p->fcap = 0;
     const int64_t W = p->width;
     HCHK(hipMalloc(&p->XT, MLP_KPAD * M * sizeof(bf16)));
     HCHK(hipMalloc(&p->HTb, p->depth * W * M * sizeof(bf16)));
     HCHK(hipMalloc(&p->DZTb, p->depth * W * M * sizeof(bf16)));
-    HCHK(hipMalloc(&p->fslab, FT_S * p->np * sizeof(float)));
     HCHK(hipMalloc(&p->flossp, p->fgrid * sizeof(float)));
     HCHK(hipMalloc(&p->fopart, (W + 1) * (M / FT_R) * sizeof(float)));
     HCHK(hipMalloc(&p->fbar, 64 * sizeof(unsigned)));
@@ -1317,7 +1329,6 @@ static int fused_step(me_mlp* p, const float* x, const float* t, const int32_t* 
     a.np = p->np;
     a.XT = p->XT;
     a.opart = p->fopart;
-    a.slab = p->fslab;
     a.lossp = p->flossp;
     a.bar = p->fbar;
     a.loss = loss;
@@ -1426,7 +1437,6 @@ int mlp_free(me_mlp* p) {
     f(p->XT);
     f(p->HTb);
     f(p->DZTb);
-    f(p->fslab);
     f(p->flossp);
     f(p->fopart);
     f(p->fbar);
