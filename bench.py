@@ -51,7 +51,7 @@ def kernel_sources_digest(process):
     """Digest of the sources that make up the float64 kernel of `process`."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2503_21935_amd", "csrc")
-    for f in ("me_vertex.h", "me_process.h", "me_kernels.h", "me_launch.h", "me_lds.h", "me_coop.h",
+    for f in ("me_vertex.h", "me_process.h", "me_kernels.h", "me_launch.h", "me_lds.h", "me_coop.h", "me_qew.h",
               os.path.join("gen", f"proc_{process}.h")):
         p = os.path.join(csrc, f)
         if os.path.exists(p):
