@@ -120,22 +120,18 @@ MEV vec4<T> gluon_eps(mom4<T> k, int lam, bool outgoing) {
     T kt2 = k.x * k.x + k.y * k.y;
     T kk = sqrt(kt2 + k.z * k.z);
     T kt = sqrt(kt2);
-    T e1x, e1y, e1z, e2x, e2y;
-    if (kt > T(0)) {
-        T ikt = T(1) / kt, ikk = T(1) / kk;
-        T c = k.z * ikk;
-        e1x = c * k.x * ikt;
-        e1y = c * k.y * ikt;
-        e1z = -kt * ikk;
-        e2x = -k.y * ikt;
-        e2y = k.x * ikt;
-    } else {  // along the z axis: azimuth 0
-        e1x = (k.z >= T(0)) ? T(1) : T(-1);
-        e1y = T(0);
-        e1z = T(0);
-        e2x = T(0);
-        e2y = T(1);
-    }
+    // Along the z axis (the beams) the azimuth is taken as 0.  Both cases are
+    // computed and selected without a branch: the off-axis values are the
+    // same operations as in a branch, and a branch here makes the compiler
+    // spill around it in every helicity.
+    const bool axis = !(kt > T(0));
+    const T ikt = T(1) / kt, ikk = T(1) / kk;
+    const T c = k.z * ikk;
+    const T e1x = axis ? ((k.z >= T(0)) ? T(1) : T(-1)) : c * k.x * ikt;
+    const T e1y = axis ? T(0) : c * k.y * ikt;
+    const T e1z = axis ? T(0) : -kt * ikk;
+    const T e2x = axis ? T(0) : -k.y * ikt;
+    const T e2y = axis ? T(1) : k.x * ikt;
     const T r2 = T(0.70710678118654752440);
     T s = -T(lam) * r2;
     T ims = outgoing ? r2 : -r2;  // imaginary part coefficient of e2
@@ -153,26 +149,20 @@ MEV vec4<T> gluon_eps(mom4<T> k, int lam, bool outgoing) {
 template <typename T>
 MEV void helicity_chi(mom4<T> p, T pabs, int lam, cx<T>& c0, cx<T>& c1) {
     T pt2 = p.x * p.x + p.y * p.y;
-    T ppz = (p.z >= T(0)) ? pabs + p.z : pt2 / (pabs - p.z);
-    if (pt2 > T(0) || p.z > T(0)) {
-        T n = T(1) / sqrt(T(2) * pabs * ppz);
-        T c = ppz * n;  // cos(th/2)
-        cx<T> se = mk(p.x * n, p.y * n);  // e^{i ph} sin(th/2)
-        if (lam > 0) {
-            c0 = mk(c, T(0));
-            c1 = se;
-        } else {
-            c0 = -conj(se);
-            c1 = mk(c, T(0));
-        }
-    } else {  // along -z: theta = pi, azimuth 0
-        if (lam > 0) {
-            c0 = mk(T(0), T(0));
-            c1 = mk(T(1), T(0));
-        } else {
-            c0 = mk(T(-1), T(0));
-            c1 = mk(T(0), T(0));
-        }
+    // pT^2 / (|p| - p_z) is |p| + p_z without cancellation when p_z < 0;
+    // both forms are computed and one selected (no branch, as in gluon_eps)
+    const T ppz = (p.z >= T(0)) ? pabs + p.z : pt2 / (pabs - p.z);
+    const bool minus_z = !(pt2 > T(0) || p.z > T(0));  // along -z: theta = pi, azimuth 0
+    const T n = T(1) / sqrt(T(2) * pabs * ppz);
+    const T c = ppz * n;  // cos(th/2)
+    const cx<T> se = mk(p.x * n, p.y * n);  // e^{i ph} sin(th/2)
+    if (lam > 0) {
+        c0 = minus_z ? mk(T(0), T(0)) : mk(c, T(0));
+        c1 = minus_z ? mk(T(1), T(0)) : se;
+    } else {
+        const cx<T> mse = -conj(se);
+        c0 = minus_z ? mk(T(-1), T(0)) : mse;
+        c1 = minus_z ? mk(T(0), T(0)) : mk(c, T(0));
     }
 }
 
