@@ -13,6 +13,8 @@ Contents
   * ``ordered_amps``   colour-ordered partial amplitudes at one helicity
   * ``me2_dressed``    |M|^2 by explicit colour brute force (slow; few events)
   * ``channel_diagrams``, ``diagram_sums``  single Feynman diagrams (route 4)
+  * ``rambo``, ``ps_mc``  phase-space points: flat RAMBO, and multi-channel
+                        sampling of a final state with a lepton pair (ps_oracle.c)
   * ``qew_me2``, ``qew_amps``  a massless quark line with gluons and a photon/Z
                         decaying to leptons (route 5; QEW_PROCESSES, among
                         them the paper's DY+3j subprocess g ubar -> tau+ tau- g g ubar)
@@ -355,6 +357,9 @@ def _ps_lib():
     lib.oracle_event_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, dp]
     lib.oracle_rambo.argtypes = [ctypes.c_double, dp, ctypes.c_int, ctypes.c_uint64, ctypes.c_int64,
                                  ctypes.c_int64, dp, dp, dp]
+    lib.oracle_ps_mc.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, ctypes.c_uint64,
+                                 ctypes.c_int64, ctypes.c_int64, dp, dp, ctypes.POINTER(ctypes.c_int32), dp]
     return lib
 
 
@@ -389,6 +394,24 @@ def rambo(roots: float, masses, seed: int, first: int, n_evt: int, cond: bool = 
     if rc != 0:
         raise ValueError("oracle_rambo: bad arguments")
     return (mom, wt, cd) if cond else (mom, wt)
+
+
+def ps_mc(roots: float, n: int, pair, window, mz: float, wz: float, alpha, seed: int, first: int, n_evt: int):
+    """Multi-channel points (flat RAMBO, a Z Breit-Wigner and a photon 1/M^2
+    channel on the invariant mass of the final-state pair (a, b), massless
+    finals): momenta [n_evt][n + 2][4], multi-channel weights, the channel of
+    each point and the weight its channel alone gives it."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    mom = np.empty((n_evt, n + 2, 4))
+    wt = np.empty(n_evt)
+    ch = np.empty(n_evt, dtype=np.int32)
+    wc = np.empty(n_evt)
+    rc = _ps_lib().oracle_ps_mc(float(roots), int(n), int(pair[0]), int(pair[1]), float(window[0]),
+                                float(window[1]), float(mz), float(wz), _ptr(a), int(seed), int(first), int(n_evt),
+                                _ptr(mom), _ptr(wt), ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(wc))
+    if rc != 0:
+        raise ValueError("oracle_ps_mc: bad arguments")
+    return mom, wt, ch, wc
 
 
 # --------------------------------------------------------------------------

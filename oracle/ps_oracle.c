@@ -183,3 +183,207 @@ int oracle_rambo(double roots, const double* m, int n, uint64_t seed, int64_t fi
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Multi-channel sampling for a final state with a lepton pair          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Three channels for n final particles of which two (a, b) come from a
+ * photon or Z (all final particles massless, n >= 3):
+ *   0: flat RAMBO over the n particles (density 1/V_n, V_n the massless
+ *      volume above);
+ *   1: the pair's invariant mass squared M^2 from a Breit-Wigner of (MZ, WZ)
+ *      restricted to [mlo^2, mhi^2] (inverse CDF through the arctangent),
+ *      RAMBO over n-1 bodies (the pair as one particle of mass M first, the
+ *      other finals in order), and an isotropic decay of the pair in its rest
+ *      frame (particle a along (cos t = 2u - 1, phi = 2 pi u'));
+ *   2: the same with M^2 distributed as 1/M^2 on the window (the photon).
+ * From the factorisation dPhi_n = dPhi_{n-1}(P; Q, ...) dQ^2/(2 pi)
+ * dPhi_2(Q; a, b), a channel-c point has density
+ *   g_c(x) = 2 pi p_c(M^2) / (w_R(x') Phi_2),   Phi_2 = 1/(8 pi),
+ * with w_R(x') the massive RAMBO weight of the (n-1)-body configuration x'
+ * = (p_a + p_b, the others), which depends on the momenta only.  The point's
+ * weight is 1 / sum_c alpha_c g_c(x) (alpha normalised), whichever channel
+ * made it; g_1 = g_2 = 0 outside the window.
+ *
+ * Random numbers of event e (Philox stream as above): particle i of the
+ * RAMBO stage takes uniforms 4i .. 4i + 3; uniform 32 picks the channel,
+ * 33 maps M^2, 34 and 35 give the decay angles.
+ */
+static double rambo_w0(int n, double s) {
+    return pow(2 * M_PI, 4 - 3 * n) * pow(M_PI / 2, n - 1) * pow(s, n - 2) / (factorial(n - 1) * factorial(n - 2));
+}
+
+/* RAMBO from uniforms u (4 per particle): n momenta p[n][4] with masses m,
+ * summing to (roots, 0, 0, 0); returns the weight. */
+static double rambo_from(double roots, const double* m, int n, const double* u, double p[][4]) {
+    double q[16][4], Q[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const double c = 2 * u[4 * i] - 1, phi = 2 * M_PI * u[4 * i + 1];
+        const double q0 = -log(u[4 * i + 2] * u[4 * i + 3]);
+        const double st = sqrt(1 - c * c);
+        q[i][0] = q0;
+        q[i][1] = q0 * st * cos(phi);
+        q[i][2] = q0 * st * sin(phi);
+        q[i][3] = q0 * c;
+        for (int k = 0; k < 4; ++k) Q[k] += q[i][k];
+    }
+    const double M = sqrt(Q[0] * Q[0] - Q[1] * Q[1] - Q[2] * Q[2] - Q[3] * Q[3]);
+    const double b[3] = {-Q[1] / M, -Q[2] / M, -Q[3] / M};
+    const double x = roots / M, gam = Q[0] / M, a = 1 / (1 + gam);
+    for (int i = 0; i < n; ++i) {
+        const double bq = b[0] * q[i][1] + b[1] * q[i][2] + b[2] * q[i][3];
+        p[i][0] = x * (gam * q[i][0] + bq);
+        for (int k = 0; k < 3; ++k) p[i][k + 1] = x * (q[i][k + 1] + b[k] * q[i][0] + a * bq * b[k]);
+    }
+    int massive = 0;
+    for (int i = 0; i < n; ++i) massive |= (m[i] != 0.0);
+    const double w0 = rambo_w0(n, roots * roots);
+    if (!massive) {
+        for (int i = 0; i < n; ++i) p[i][0] = sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+        return w0;
+    }
+    double lo = 0.0, hi = 1.0, xi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        double f = -roots, df = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double en = sqrt(m[i] * m[i] + xi * xi * p[i][0] * p[i][0]);
+            f += en;
+            df += xi * p[i][0] * p[i][0] / en;
+        }
+        if (f > 0) hi = xi;
+        else lo = xi;
+        double nx = xi - f / df;
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        if (fabs(nx - xi) <= 1e-16 * xi) {
+            xi = nx;
+            break;
+        }
+        xi = nx;
+    }
+    double sk = 0.0, pr = 1.0, sk2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int k = 1; k < 4; ++k) p[i][k] *= xi;
+        const double kk = sqrt(p[i][1] * p[i][1] + p[i][2] * p[i][2] + p[i][3] * p[i][3]);
+        p[i][0] = sqrt(m[i] * m[i] + kk * kk);
+        sk += kk;
+        pr *= kk / p[i][0];
+        sk2 += kk * kk / p[i][0];
+    }
+    return w0 * pow(sk / roots, 2 * n - 3) * pr * roots / sk2;
+}
+
+/* Massive RAMBO weight of final momenta k[n][4] (from the momenta alone). */
+static double rambo_weight_of(double roots, int n, const double k[][4]) {
+    double sk = 0.0, pr = 1.0, sk2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double kk = sqrt(k[i][1] * k[i][1] + k[i][2] * k[i][2] + k[i][3] * k[i][3]);
+        sk += kk;
+        pr *= kk / k[i][0];
+        sk2 += kk * kk / k[i][0];
+    }
+    return rambo_w0(n, roots * roots) * pow(sk / roots, 2 * n - 3) * pr * roots / sk2;
+}
+
+typedef struct {
+    double a2, b2, mz, wz, alpha[3];
+    double bw_lo, bw_hi;  /* arctangent bounds of the Breit-Wigner map */
+} mc_setup;
+
+static double mc_pdf(const mc_setup* S, int c, double m2) {
+    if (!(m2 >= S->a2 && m2 <= S->b2)) return 0.0;
+    if (c == 1) {
+        const double mw = S->mz * S->wz, d = m2 - S->mz * S->mz;
+        return mw / (d * d + mw * mw) / (S->bw_hi - S->bw_lo);
+    }
+    return 1.0 / (m2 * log(S->b2 / S->a2));
+}
+
+/* 1 / sum_c alpha_c g_c(x) for final momenta f[n][4], pair (ia, ib). */
+static double mc_weight_of(const mc_setup* S, double roots, int n, const double f[][4], int ia, int ib) {
+    double g = S->alpha[0] / rambo_w0(n, roots * roots);
+    double P[4];
+    for (int k = 0; k < 4; ++k) P[k] = f[ia][k] + f[ib][k];
+    const double m2 = P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3];
+    if (m2 >= S->a2 && m2 <= S->b2 && (S->alpha[1] > 0 || S->alpha[2] > 0)) {
+        double k[16][4];
+        int j = 0;
+        memcpy(k[j++], P, sizeof(P));
+        for (int i = 0; i < n; ++i)
+            if (i != ia && i != ib) memcpy(k[j++], f[i], sizeof(P));
+        const double wr = rambo_weight_of(roots, n - 1, (const double(*)[4])k);
+        const double phi2 = 1.0 / (8 * M_PI);
+        for (int c = 1; c < 3; ++c) g += S->alpha[c] * 2 * M_PI * mc_pdf(S, c, m2) / (wr * phi2);
+    }
+    return 1.0 / g;
+}
+
+/* Events first .. first + nevt - 1: momenta [nevt][n + 2][4] as ps_rambo,
+ * weights [nevt], chan [nevt] (may be NULL), wc [nevt] (may be NULL): the
+ * weight of the generating channel alone, 1/g_c, from its construction.
+ * Returns 0, or -1 on bad arguments. */
+int oracle_ps_mc(double roots, int n, int ia, int ib, double mlo, double mhi, double mz, double wz,
+                 const double* alpha, uint64_t seed, int64_t first, int64_t nevt, double* mom, double* wt,
+                 int32_t* chan, double* wc) {
+    if (n < 3 || n > 15 || ia < 0 || ib < 0 || ia >= n || ib >= n || ia == ib || nevt < 0 || roots <= 0) return -1;
+    if (!(mlo > 0 && mhi > mlo && mhi <= roots)) return -1;
+    const double at = alpha[0] + alpha[1] + alpha[2];
+    if (!(alpha[0] >= 0 && alpha[1] >= 0 && alpha[2] >= 0 && at > 0)) return -1;
+    mc_setup S;
+    S.a2 = mlo * mlo;
+    S.b2 = mhi * mhi;
+    S.mz = mz;
+    S.wz = wz;
+    for (int c = 0; c < 3; ++c) S.alpha[c] = alpha[c] / at;
+    S.bw_lo = atan((S.a2 - mz * mz) / (mz * wz));
+    S.bw_hi = atan((S.b2 - mz * mz) / (mz * wz));
+    for (int64_t e = 0; e < nevt; ++e) {
+        double u[36];
+        oracle_event_uniforms(seed, (uint64_t)(first + e), 36, u);
+        const int c = (u[32] < S.alpha[0]) ? 0 : (u[32] < S.alpha[0] + S.alpha[1]) ? 1 : 2;
+        double f[16][4];
+        double w_own;
+        if (c == 0) {
+            double m0[16] = {0};
+            w_own = rambo_from(roots, m0, n, u, f);
+        } else {
+            double m2;
+            if (c == 1) {
+                const double t = S.bw_lo + u[33] * (S.bw_hi - S.bw_lo);
+                m2 = mz * mz + mz * wz * tan(t);
+            } else {
+                m2 = S.a2 * pow(S.b2 / S.a2, u[33]);
+            }
+            const double M = sqrt(m2);
+            double m1[16] = {0}, k[16][4];
+            m1[0] = M;
+            const double wr = rambo_from(roots, m1, n - 1, u, k);
+            /* decay of the pair (k[0], mass M) in its rest frame */
+            const double ct = 2 * u[34] - 1, ph = 2 * M_PI * u[35], st = sqrt(1 - ct * ct);
+            const double es = 0.5 * M;
+            const double ks[3] = {es * st * cos(ph), es * st * sin(ph), es * ct};
+            const double pk = k[0][1] * ks[0] + k[0][2] * ks[1] + k[0][3] * ks[2];
+            const double e0 = (k[0][0] * es + pk) / M;
+            const double fac = (e0 + es) / (k[0][0] + M);
+            f[ia][0] = e0;
+            for (int j = 0; j < 3; ++j) f[ia][j + 1] = ks[j] + fac * k[0][j + 1];
+            for (int j = 0; j < 4; ++j) f[ib][j] = k[0][j] - f[ia][j];
+            int jj = 1;
+            for (int i = 0; i < n; ++i)
+                if (i != ia && i != ib) memcpy(f[i], k[jj++], sizeof(f[i]));
+            /* massless products: energies from the 3-momenta */
+            f[ia][0] = sqrt(f[ia][1] * f[ia][1] + f[ia][2] * f[ia][2] + f[ia][3] * f[ia][3]);
+            f[ib][0] = sqrt(f[ib][1] * f[ib][1] + f[ib][2] * f[ib][2] + f[ib][3] * f[ib][3]);
+            w_own = wr / (8 * M_PI) / (2 * M_PI * mc_pdf(&S, c, m2));
+        }
+        double* o = mom + e * (int64_t)(n + 2) * 4;
+        o[0] = roots / 2, o[1] = 0, o[2] = 0, o[3] = roots / 2;
+        o[4] = roots / 2, o[5] = 0, o[6] = 0, o[7] = -roots / 2;
+        for (int i = 0; i < n; ++i) memcpy(o + 4 * (i + 2), f[i], sizeof(f[i]));
+        if (wt) wt[e] = mc_weight_of(&S, roots, n, (const double(*)[4])f, ia, ib);
+        if (chan) chan[e] = c;
+        if (wc) wc[e] = w_own;
+    }
+    return 0;
+}
