@@ -164,6 +164,69 @@ def bench_phase_space(me, stream, n, host_s):
             "host_numpy_rambo_s_same_size": host_s}
 
 
+def bench_ps_multichannel(me, stream, n, steps):
+    """Multi-channel phase space for the DY+3j subprocess g ubar -> tau+ tau-
+    g g ubar at sqrt(s) = 13 TeV (2^20 points; flat, Z Breit-Wigner and photon
+    1/M^2 channels on the tau-pair mass, window 50 GeV .. sqrt(s)): sampler
+    throughput, then the integral of |M|^2 with the generator cuts on the
+    partons, estimated from the same number of flat RAMBO points and of
+    multi-channel points.  Reported per sampler: the estimate, its relative
+    standard error, the effective sample fraction (sum f)^2 / (N sum f^2) and
+    the unweighting efficiency mean(f) / max(f) of f = w |M|^2."""
+    import numpy as np
+    import torch
+
+    from inputs import gluon_cuts
+
+    proc, roots, nf, pair, window = "gux_taptamggux", 13000.0, 5, (0, 1), (50.0, 13000.0)
+    mz, wz = me.DEFAULT_MASSES[0], me.DEFAULT_MASSES[1]  # the matrix element's Z mass and width
+    alpha = (0.3, 0.4, 0.3)
+    mom = torch.empty((n, nf + 2, 4), dtype=torch.float64, device="cuda")
+    wt = torch.empty(n, dtype=torch.float64, device="cuda")
+    ch = torch.empty(n, dtype=torch.int32, device="cuda")
+
+    def sample(seed):
+        me.ps_multichannel(roots, nf, pair, window, mz, wz, alpha, seed, 0, n, mom, wt, ch, stream)
+
+    sample(6)
+    k_s, _ = timed(lambda: sample(6), steps, stream)
+    nbytes = n * ((nf + 2) * 4 * 8 + 8 + 4)
+    m = me.MatrixElement(proc)
+    me2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    stats = {}
+    for name in ("flat", "multichannel"):
+        if name == "flat":
+            me.ps_rambo(roots, [0.0] * nf, 6, 0, n, mom, wt, stream)
+        else:
+            sample(6)
+        m.eval(mom, out=me2, stream=stream)
+        mom_np = mom.cpu().numpy()
+        P = mom_np[:, 2 + pair[0]] + mom_np[:, 2 + pair[1]]
+        mll2 = P[:, 0] ** 2 - (P[:, 1:] ** 2).sum(-1)
+        ok = gluon_cuts(mom_np) & (mll2 >= window[0] ** 2)
+        f = np.where(ok, wt.cpu().numpy() * me2.cpu().numpy(), 0.0)
+        mean = f.mean()
+        near_z = ok & (np.abs(np.sqrt(np.maximum(mll2, 0.0)) - mz) < 10.0)
+        stats[name] = {"estimate": float(mean), "rel_std_error": float(f.std() / (mean * np.sqrt(n))),
+                       "effective_sample_fraction": float(f.sum() ** 2 / (n * (f ** 2).sum())),
+                       "unweighting_efficiency": float(mean / f.max()), "points_passing_cuts": int(ok.sum()),
+                       "points_within_10_GeV_of_MZ": int(near_z.sum()),
+                       "share_of_estimate_within_10_GeV_of_MZ": float(f[near_z].sum() / f.sum())}
+        if name == "multichannel":
+            stats[name]["channel_counts"] = np.bincount(ch.cpu().numpy(), minlength=3).tolist()
+    m.close()
+    fl, mc = stats["flat"], stats["multichannel"]
+    return {"workload": f"{n} {proc} points, sqrt(s) = 13 TeV, pair-mass window {window[0]:g} GeV .. sqrt(s), "
+                        f"alpha {alpha}", "kernel": f"k_ps_mc<{nf}>", "points_per_s": n / k_s,
+            "kernel_ms": k_s * 1e3,
+            "roofline": {"bound": "hbm", "achieved": nbytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": nbytes // n},
+            "flat": fl, "multichannel": mc,
+            "variance_gain": (fl["rel_std_error"] / mc["rel_std_error"]) ** 2,
+            "estimates_differ_by_sigma": float(abs(fl["estimate"] - mc["estimate"]) / np.hypot(
+                fl["rel_std_error"] * fl["estimate"], mc["rel_std_error"] * mc["estimate"]))}
+
+
 def bench_colour_forms(me, stream, cases):
     """Float64 kernel time with the colour sum on the VALU (symmetric form) and
     as a float64 MFMA GEMM over block pairs (me_set_colour_form)."""
@@ -523,12 +586,13 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5, help="mixed form: per-event relative tolerance")
     ap.add_argument("--check", type=int, default=2048, help="mixed form: events checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=1 << 16, help="events for the CPU oracle baseline")
-    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,dy3j,configs,sweep,ps,colour,mc",
+    ap.add_argument("--forms", default="fp64,mixed,surrogate,gg_ttggg,dy3j,configs,sweep,ps,psmc,colour,mc",
                     help="gg_ttggg: also time the float64 kernel of g g -> t tbar g g g (2^18 points, seed 3); "
                          "dy3j: g ubar -> tau+ tau- g g ubar, the DY+3j subprocess (2^20 points, seed 4); "
                          "configs: e+e- -> mu+mu- (16384 points, seed 0) and g g -> t tbar (2^20, seed 1); "
                          "sweep: events per launch 2^10..2^20 at 1, 4, 16, 64 lanes per event; "
                          "ps: the GPU phase-space sampler on the benchmark's workload; "
+                         "psmc: multi-channel phase space for the DY+3j subprocess, and its variance against flat; "
                          "colour: float64 kernels with the colour sum on the VALU and on the matrix cores; "
                          "mc: the multi-channel form (single-diagram weights)")
     ap.add_argument("--cpu-sample-1t", type=int, default=4096, help="events for the single-thread oracle figure")
@@ -642,6 +706,9 @@ def main():
     if "ps" in forms:
         line["phase_space"] = bench_phase_space(me, stream, args.nevt, host_gen_s)
         log(f"phase space: {line['phase_space']['points_per_s']:.3e} points/s")
+    if "psmc" in forms:
+        line["phase_space_multichannel"] = bench_ps_multichannel(me, stream, 1 << 20, 20)
+        log(f"multi-channel phase space: {line['phase_space_multichannel']}")
     if "sweep" in forms:
         line["nevt_sweep"] = nevt_sweep(me, args.process, args.seed, [1, 4, 16, 64], list(range(10, 21, 2)), stream)
 

@@ -50,6 +50,48 @@ extern "C" {
 int ps_rambo(double roots, const double *masses, int nfinal, uint64_t seed, int64_t first_event, int64_t nevt,
              double *momenta, double *weights, void *stream);
 
+/*
+ * ps_multichannel -- nevt phase-space points for a final state with a lepton
+ * pair, sampled from three channels and weighted by the multi-channel weight.
+ * The paper names faster phase-space sampling on the GPU as the next step
+ * (Sec. 3, outlook); for a pair produced through a photon or a Z boson, flat
+ * sampling wastes most points away from the pair-mass peaks.
+ *
+ * Channels (alpha normalised to sum 1):
+ *   0: flat RAMBO over the nfinal particles (as ps_rambo, massless);
+ *   1: the pair mass squared M^2 from a Breit-Wigner of (mz, wz) on the
+ *      window [mlo^2, mhi^2] (arctangent map), then flat RAMBO over
+ *      nfinal - 1 bodies (the pair as one particle of mass M first, the other
+ *      finals in order), and an isotropic two-body decay of the pair in its
+ *      rest frame;
+ *   2: the same with M^2 distributed as 1/M^2 on the window (logarithmic map,
+ *      the photon).
+ * Each point's weight is 1 / sum_c alpha_c g_c(x), g_0 = 1 / V_n (V_n the
+ * massless n-body volume) and, from the factorisation
+ * dPhi_n = dPhi_{n-1} dM^2/(2 pi) dPhi_2 with Phi_2 = 1/(8 pi),
+ * g_c = 2 pi p_c(M^2) / (w_R(x') Phi_2) for c = 1, 2 inside the window (0
+ * outside), w_R(x') the massive RAMBO weight of the (n-1)-body configuration
+ * (p_a + p_b, the others).  The weight is computed from the final momenta
+ * alone, whichever channel made the point, so the sample estimates
+ * integrals over flat phase space without bias (Kleiss, Pittau, Comput. Phys.
+ * Commun. 83 (1994) 141).
+ *
+ * roots: sqrt(s) in GeV.  nfinal: 3..8.  pair_a, pair_b: final-state indices
+ * (0-based, distinct) of the lepton pair.  mlo, mhi: the pair-mass window
+ * (0 < mlo < mhi <= roots).  mz, wz: resonance mass and width (> 0).
+ * alpha: host array of 3 channel weights (>= 0, positive sum).
+ * seed, first_event: the Philox stream of ps_rambo; RAMBO particle i takes
+ * uniforms 4i .. 4i + 3, uniform 32 picks the channel, 33 maps M^2, 34 and 35
+ * give the decay angles (cos theta = 2u - 1, phi = 2 pi u').
+ * momenta: device float64 [nevt][nfinal + 2][4], 16-byte aligned, layout of
+ * ps_rambo.  weights: device float64 [nevt] or NULL.  channels: device int32
+ * [nevt] or NULL, the channel that made each point.
+ * Errors: ME_EINVAL (sizes, window, channel weights, alignment), ME_EDEVICE.
+ */
+int ps_multichannel(double roots, int nfinal, int pair_a, int pair_b, double mlo, double mhi, double mz, double wz,
+                    const double *alpha, uint64_t seed, int64_t first_event, int64_t nevt, double *momenta,
+                    double *weights, int32_t *channels, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -373,6 +373,39 @@ def ps_rambo(roots, masses, seed, first_event, nevt, momenta, weights=None, stre
                       _stream_handle(stream)), "ps_rambo")
 
 
+def ps_multichannel(roots, nfinal, pair, window, mz, wz, alpha, seed, first_event, nevt, momenta, weights=None,
+                    channels=None, stream=None) -> None:
+    L = lib()
+    if not getattr(L, "_ps_mc_ready", False):
+        d, vp = ctypes.c_double, ctypes.c_void_p
+        L.ps_multichannel.argtypes = [d, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, d, d,
+                                      ctypes.POINTER(d), ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, vp, vp,
+                                      vp, vp]
+        L._ps_mc_ready = True
+    nevt = _nevt(nevt)
+    _need(momenta, nevt * (nfinal + 2) * 4, "momenta")
+    _need(weights, nevt, "weights")
+    _need(channels, nevt, "channels")
+    a = (ctypes.c_double * 3)(*[float(v) for v in alpha])
+    _check(L.ps_multichannel(float(roots), int(nfinal), int(pair[0]), int(pair[1]), float(window[0]),
+                             float(window[1]), float(mz), float(wz), a, int(seed), int(first_event), nevt,
+                             _dev_ptr(momenta, "float64", "momenta"), _opt_ptr(weights, "float64", "weights"),
+                             _opt_ptr(channels, "int32", "channels"), _stream_handle(stream)), "ps_multichannel")
+
+
+def multichannel(roots, nfinal, pair, window, mz, wz, alpha, seed, n, first_event=0, device="cuda", stream=None):
+    """Multi-channel phase-space points for a final state with a lepton pair
+    (flat, Breit-Wigner and 1/M^2 channels on the pair mass), generated on the
+    GPU: (momenta [n][nfinal + 2][4], weights [n], channels [n])."""
+    import torch
+
+    mom = torch.empty((n, nfinal + 2, 4), dtype=torch.float64, device=device)
+    wt = torch.empty(n, dtype=torch.float64, device=device)
+    ch = torch.empty(n, dtype=torch.int32, device=device)
+    ps_multichannel(roots, nfinal, pair, window, mz, wz, alpha, seed, first_event, n, mom, wt, ch, stream)
+    return mom, wt, ch
+
+
 def rambo(roots, masses, seed, n, first_event=0, device="cuda", stream=None):
     """Flat phase-space points generated on the GPU: (momenta [n][nf + 2][4],
     weights [n]) as float64 device tensors."""
