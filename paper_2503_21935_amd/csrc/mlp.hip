@@ -439,7 +439,7 @@ struct ft_args {
     int n_in, depth;
     bf16* wfr[FT_MAXDEPTH];   // W_l [256][ld] in fragment order (ld 32 for the first layer)
     bf16* wtfr[FT_MAXDEPTH];  // W_l^T [fan_in][256] in fragment order (layers >= 1)
-    bf16* wbf[FT_MAXDEPTH];   // row-major BF16 copies (other kernels), refreshed with them
+    bf16* wbf[FT_MAXDEPTH];   // row-major BF16 copies (other kernels), written by the launch's last step
     bf16* wbft[FT_MAXDEPTH];
     float* theta;             // FP32 masters (flat layout)
     float *m, *v;             // Adam moments
@@ -465,8 +465,7 @@ __device__ __forceinline__ float silu_d(float z) {
 }
 
 // B fragments of rows 64 wave + 16 t + 0..15 of the [256][K] matrix Wm kept in
-// fragment order (K / 32 MFMA k-steps).  Loaded one layer ahead: the loads of the next
-// product are in flight during the current layer's epilogue.
+// fragment order (K / 32 MFMA k-steps).
 template <int K>
 __device__ __forceinline__ void ft_load_w(const bf16* __restrict__ Wm, int wave, int lane, bf16x8 (&b)[8][4]) {
 #pragma unroll
@@ -487,6 +486,15 @@ __device__ __forceinline__ void ft_mma(const bf16* A, const bf16x8 (&b)[8][4], i
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[ks][t], acc[t], 0, 0, 0);
     }
+}
+
+// The weights of product k of a tile's chain after the first layer (k = 1 ..
+// 2 (depth - 1)): W_k forward for k < depth, then W_l^T backward for l =
+// depth - 1 .. 1; nullptr past the end.
+__device__ __forceinline__ const bf16* ft_chain_w(const bf16* const* wfr, const bf16* const* wtfr, int depth, int k) {
+    if (k <= depth - 1) return wfr[k];
+    if (k <= 2 * (depth - 1)) return wtfr[2 * depth - 1 - k];
+    return nullptr;
 }
 
 // Grid-wide barrier of a cooperative launch (every block resident).  Each
@@ -598,7 +606,11 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
     const int li = lane & 15, lg = lane >> 4;
     const int64_t M = a.M;
     const int nrt = (int)(M / FT_R);
-    bf16x8 bw0[8][4], bw[8][4];  // first-layer and current-layer B fragments (bw0: one k-step)
+    // B fragments: bw0 the first layer's (one k-step); the products after it
+    // alternate between bwa (odd) and bwb (even), and the weights of product
+    // k + 2 are loaded into a buffer as soon as product k has used it, so
+    // every load has a whole layer's work to arrive
+    bf16x8 bw0[8][4], bwa[8][4], bwb[8][4];
     bool first_in_lds = false;   // the step's first tile is already in Hs / tgs
     for (int st = 0; st < a.nsteps; ++st) {
         float* loss = a.loss ? a.loss + st : nullptr;
@@ -613,8 +625,11 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
         // ---------------- phase 1: rows through forward and backward ----------------
         for (int rt = blockIdx.x; rt < nrt; rt += gridDim.x) {
             const int64_t m0 = (int64_t)rt * FT_R;
-            ft_load_w<MLP_KPAD>(a.wfr[0], wave, lane, bw0);
-            if (a.depth > 1) ft_load_w<W>(a.wfr[1], wave, lane, bw);
+            const bf16* const* wfr = a.wfr;
+            const bf16* const* wtfr = a.wtfr;
+            ft_load_w<MLP_KPAD>(wfr[0], wave, lane, bw0);
+            if (const bf16* w1 = ft_chain_w(wfr, wtfr, a.depth, 1)) ft_load_w<W>(w1, wave, lane, bwa);
+            if (const bf16* w2 = ft_chain_w(wfr, wtfr, a.depth, 2)) ft_load_w<W>(w2, wave, lane, bwb);
             if (!(first_in_lds && rt == (int)blockIdx.x)) {
                 ft_rows g;
                 ft_rows_load(a, st, m0, tid, g);
@@ -622,17 +637,18 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
             }
             __syncthreads();
             if (tid < MLP_KPAD) ft_store_t(Hs, tid, a.XT, M, m0);
-            for (int l = 0; l < a.depth; ++l) {
+#pragma unroll
+            for (int l = 0; l < FT_MAXDEPTH; ++l) {
+                if (l >= a.depth) break;
                 f32x4 acc[4];
                 if (l == 0) {
                     ft_mma<MLP_KPAD>(Hs, bw0, li, lg, acc);
+                } else if (l & 1) {  // product l
+                    ft_mma<W>(Hs, bwa, li, lg, acc);
+                    if (const bf16* wn = ft_chain_w(wfr, wtfr, a.depth, l + 2)) ft_load_w<W>(wn, wave, lane, bwa);
                 } else {
-                    ft_mma<W>(Hs, bw, li, lg, acc);
-                    // the next product's weights: the next layer, or the first backward layer
-                    if (l + 1 < a.depth)
-                        ft_load_w<W>(a.wfr[l + 1], wave, lane, bw);
-                    else
-                        ft_load_w<W>(a.wtfr[a.depth - 1], wave, lane, bw);
+                    ft_mma<W>(Hs, bwb, li, lg, acc);
+                    if (const bf16* wn = ft_chain_w(wfr, wtfr, a.depth, l + 2)) ft_load_w<W>(wn, wave, lane, bwb);
                 }
                 __syncthreads();  // the layer input has been read by every wave
 #pragma unroll
@@ -687,10 +703,19 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
             __syncthreads();
             ft_store_t(Gs, tid, a.DZT[a.depth - 1], M, m0);
             // backward through the hidden layers: dZ_{l-1} = (dZ_l W_l) silu'(Z_{l-1})
-            for (int l = a.depth - 1; l >= 1; --l) {
+            // (product 2 depth - 1 - l: bwa when l is even)
+#pragma unroll
+            for (int l = FT_MAXDEPTH - 1; l >= 1; --l) {
+                if (l >= a.depth) continue;
                 f32x4 acc[4];
-                ft_mma<W>(Gs, bw, li, lg, acc);
-                if (l > 1) ft_load_w<W>(a.wtfr[l - 1], wave, lane, bw);
+                const int k = 2 * a.depth - 1 - l;
+                if ((l & 1) == 0) {
+                    ft_mma<W>(Gs, bwa, li, lg, acc);
+                    if (const bf16* wn = ft_chain_w(wfr, wtfr, a.depth, k + 2)) ft_load_w<W>(wn, wave, lane, bwa);
+                } else {
+                    ft_mma<W>(Gs, bwb, li, lg, acc);
+                    if (const bf16* wn = ft_chain_w(wfr, wtfr, a.depth, k + 2)) ft_load_w<W>(wn, wave, lane, bwb);
+                }
                 __syncthreads();  // Gs has been read by every wave
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -866,11 +891,14 @@ __global__ __launch_bounds__(256, 1) void k_mlp_train_fused(ft_args a) {
                     continue;
                 }
                 const float t2 = ft_adam(a, i, g[r], mo[r], vo[r], th[r], lr, c1, c2);
-                a.wbf[l][rr * ld + kk] = (bf16)t2;
+                // the fragment-order copies feed the next step; the row-major
+                // ones only other kernels, so they are written by the last step
+                const bool last = st + 1 == a.nsteps;
                 a.wfr[l][frag_off(rr, kk, ld)] = (bf16)t2;
+                if (last) a.wbf[l][rr * ld + kk] = (bf16)t2;
                 if (l > 0) {
-                    a.wbft[l][kk * W + rr] = (bf16)t2;
                     a.wtfr[l][frag_off(kk, rr, W)] = (bf16)t2;
+                    if (last) a.wbft[l][kk * W + rr] = (bf16)t2;
                 }
             }
             if (kb == 0 && tid < 32) {
