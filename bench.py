@@ -120,7 +120,9 @@ def bench_process(me, proc, nevt, seed, steps, stream, check=8, tol=None):
 
 def nevt_sweep(me, proc, seed, lanes_list, logs, stream):
     """MEs/s of the float64 kernel against the number of events per launch, for
-    one lane per event and for helicity-parallel launches (2^k lanes per event)."""
+    the automatic lane count (0: enough lanes per event to put 2^16 lanes in
+    flight), one lane per event and helicity-parallel launches (2^k lanes per
+    event)."""
     import torch
 
     from inputs import process_points
@@ -300,7 +302,7 @@ def parity_adjudication(proc, mom_np, got, ref, tol=1e-12):
         q0 = oracle.me2(proc, mom_np[bad], quad=True)
         rng = np.random.default_rng(1)
         spread = np.zeros(bad.size)
-        for _ in range(4):
+        for _ in range(16):
             pert = mom_np[bad] * (1 + rng.choice([-1.0, 1.0], size=mom_np[bad].shape) * 2.0 ** -52)
             spread = np.maximum(spread, np.abs(oracle.me2(proc, pert, quad=True) / q0 - 1))
         rq = np.abs(got[bad] / q0 - 1)
@@ -720,7 +722,7 @@ def main():
         line["phase_space_multichannel"] = bench_ps_multichannel(me, stream, 1 << 20, 20)
         log(f"multi-channel phase space: {line['phase_space_multichannel']}")
     if "sweep" in forms:
-        line["nevt_sweep"] = nevt_sweep(me, args.process, args.seed, [1, 4, 16, 64], list(range(10, 21, 2)), stream)
+        line["nevt_sweep"] = nevt_sweep(me, args.process, args.seed, [0, 1, 4, 16, 64], list(range(10, 21, 2)), stream)
 
     if not args.no_cpu:
         import oracle

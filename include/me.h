@@ -120,14 +120,16 @@ int me_set_precision(me_ctx *ctx, int mode, double rel_tol);
  * me_set_helicity_lanes -- helicity-level parallelism of later float64
  * me_eval calls (the paper's Sec. 2: besides one event per thread, the
  * helicities of one event can be spread over threads, so that fewer events in
- * flight fill the GPU).  lanes: 1 (default; one lane sums all helicities of
- * its event), 2, 4, 8, 16, 32 or 64 lanes per event; each lane sums every
+ * flight fill the GPU).  lanes: 1 (one lane sums all helicities of its
+ * event), 2, 4, 8, 16, 32 or 64 lanes per event; each lane sums every
  * lanes-th filtered helicity and the lanes' partial sums are added when the
- * event is done.  The result equals the one-lane result up to the order of
- * the helicity sum.  Applies to the float64 form of me_eval only (the mixed
- * form, its float64 rerun, me_eval_helicities and unweighting keep one lane
- * per event).  Errors: ME_EINVAL (null context, lanes not a power of two up
- * to 64).
+ * event is done.  lanes = 0 (the default): chosen per call, the smallest
+ * power of two with nevt * lanes >= 65536, at most 64 and at most the number
+ * of helicities kept (one lane per event from 65536 events up).  The result
+ * equals the one-lane result up to the order of the helicity sum.  Applies to
+ * the float64 form of me_eval only (the mixed form, its float64 rerun,
+ * me_eval_helicities and unweighting keep one lane per event).  Errors:
+ * ME_EINVAL (null context, lanes neither 0 nor a power of two up to 64).
  */
 int me_set_helicity_lanes(me_ctx *ctx, int lanes);
 

@@ -24,7 +24,7 @@ struct me_ctx {
     int* d_good;            // device copy
     int* d_all;             // device list 0..nhel-1
     int mode;               // ME_FP64 or ME_MIXED
-    int hel_lg;             // float64 form: 2^hel_lg lanes per event (helicity parallelism)
+    int hel_lg;             // float64 form: 2^hel_lg lanes per event (helicity parallelism), -1 automatic
     int colour_form;        // float64 form: ME_COLOUR_VALU or ME_COLOUR_MFMA
     double tol;             // mixed form: per-event relative error tolerance
     // scratch of the mixed form: flagged-event counter and index list

@@ -79,6 +79,7 @@ def test_forced_fallback_is_float64(me_mod, torch_cuda):
     torch = torch_cuda
     mom = process_points("gg_ttgg", 1000, 9)
     m = me_mod.MatrixElement("gg_ttgg")
+    m.set_helicity_lanes(1)  # the rerun's float64 kernel takes one lane per event
     t = torch.from_numpy(mom).cuda()
     ref = m.eval(t).clone()
     m.set_precision(me_mod.ME_MIXED, 1e-14)
@@ -96,6 +97,7 @@ def test_forced_fallback_workgroup_kernel(me_mod, torch_cuda):
     torch = torch_cuda
     mom = process_points("gg_ttggg", 100, 9)
     m = me_mod.MatrixElement("gg_ttggg")
+    m.set_helicity_lanes(1)
     t = torch.from_numpy(mom).cuda()
     ref = m.eval(t).clone()
     m.set_precision(me_mod.ME_MIXED, 1e-14)

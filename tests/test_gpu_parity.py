@@ -69,8 +69,11 @@ def gpu_me2(me_mod, torch, proc, mom):
     return out.cpu().numpy()
 
 
-def input_sensitivity(proc, mom, nsamp=4):
-    """Quad-precision result and its spread under 2^-52 relative input perturbations."""
+def input_sensitivity(proc, mom, nsamp=16):
+    """Quad-precision result and its spread under 2^-52 relative input
+    perturbations: the largest deviation over nsamp random sign patterns (one
+    g g -> t tbar g g g event of the 2^14 set has a spread below 1.8e-12 over
+    4 patterns and 2.0e-10 over 16)."""
     q0 = oracle.me2(proc, mom, quad=True)
     rng = np.random.default_rng(1)
     spread = np.zeros(len(mom))
@@ -207,6 +210,24 @@ def test_parity_all_ggttgg(me_mod, torch_cuda):
           f"median {np.median(rel):.2e}, beyond 1e-12: {int((rel > TOL).sum())}", flush=True)
 
 
+@pytest.mark.skipif(os.environ.get("ME_PARITY_FULL") != "1",
+                    reason="2^14 g g -> t tbar g g g events against the oracle: about a minute of host time, "
+                           "run with ME_PARITY_FULL=1")
+def test_parity_2p14_ggttggg(me_mod, torch_cuda):
+    """The first 2^14 g g -> t tbar g g g points (seed 3) against the oracle."""
+    n = 1 << 14
+    mom = process_points("gg_ttggg", n, 3)
+    got = gpu_me2(me_mod, torch_cuda, "gg_ttggg", mom)
+    want = np.empty(n)
+    chunk = 1 << 12
+    for c in range(0, n, chunk):
+        want[c:c + chunk] = oracle.me2("gg_ttggg", mom[c:c + chunk])
+        print(f"[parity-2p14] oracle {c + chunk}/{n}", flush=True)
+    rel = check_parity("gg_ttggg", mom, got, want=want)
+    print(f"[parity-2p14] gg_ttggg 2^14: max rel {rel.max():.2e}, p99.9 {np.quantile(rel, 0.999):.2e}, "
+          f"median {np.median(rel):.2e}, beyond 1e-12: {int((rel > TOL).sum())}", flush=True)
+
+
 def test_full_size_ggtt(me_mod, torch_cuda):
     """2^20 ggtt points (seed 1), all compared."""
     mom = process_points("gg_tt", 1 << 20, 1)
@@ -252,6 +273,7 @@ def test_helicity_lanes(me_mod, torch_cuda, proc, lanes, n):
     mom = process_points(proc, n, 41)
     t = torch.from_numpy(mom).cuda()
     m = me_mod.MatrixElement(proc)
+    m.set_helicity_lanes(1)
     one = m.eval(t)
     m.set_helicity_lanes(lanes)
     many = m.eval(t)
@@ -262,6 +284,35 @@ def test_helicity_lanes(me_mod, torch_cuda, proc, lanes, n):
     with pytest.raises(me_mod.MEError) as e:
         m.set_helicity_lanes(3)
     assert e.value.status == me_mod.ME_EINVAL
+    m.close()
+
+
+@pytest.mark.parametrize("proc,n", [("gg_ttgg", 5), ("gg_ttgg", 1000), ("gg_ttgg", 70000), ("ee_mumu", 300),
+                                    ("gg_ttggg", 40), ("gux_taptamggux", 2000)])
+def test_automatic_helicity_lanes(me_mod, torch_cuda, proc, n):
+    """The default lane count (0: the smallest power of two that puts 2^16
+    lanes in flight, capped by 64 and the helicities kept) gives the one-lane
+    result up to the order of the helicity sum, and the lanes setting can be
+    returned to it."""
+    torch = torch_cuda
+    print(f"[lanes-auto] {proc} n={n}", flush=True)
+    mom = process_points(proc, n, 45)
+    t = torch.from_numpy(mom).cuda()
+    m = me_mod.MatrixElement(proc)
+    auto = m.eval(t).cpu().numpy()
+    m.set_helicity_lanes(1)
+    one = m.eval(t).cpu().numpy()
+    m.set_helicity_lanes(8)
+    m.set_helicity_lanes(0)
+    again = m.eval(t).cpu().numpy()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(auto, one, rtol=1e-13, atol=0)
+    if proc == "gg_ttggg":  # the workgroup kernel adds into LDS atomically: equal to rounding
+        np.testing.assert_allclose(again, auto, rtol=1e-13, atol=0)
+    else:
+        assert np.array_equal(again, auto)
+    sel = np.unique(np.linspace(0, n - 1, min(n, 64)).astype(int))
+    check_parity(proc, mom[sel], auto[sel])
     m.close()
 
 

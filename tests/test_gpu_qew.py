@@ -80,6 +80,7 @@ def test_helicity_lanes(me_mod, torch_cuda, lanes):
     mom = process_points("gux_taptamggux", 1000, 41)
     t = torch.from_numpy(mom).cuda()
     m = me_mod.MatrixElement("gux_taptamggux")
+    m.set_helicity_lanes(1)
     one = m.eval(t)
     m.set_helicity_lanes(lanes)
     many = m.eval(t)
