@@ -45,7 +45,10 @@ struct epi_args {
     int ncols_store;    // DW: columns actually stored (n_in for the first layer)
 };
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.f / (1.f + __expf(-z)); }
+// Logistic function with the hardware reciprocal (v_rcp_f32, about 1 ulp):
+// a correctly rounded division costs ten instructions per activation, and the
+// value is rounded to BF16 (8 bits) or enters an FP32 gradient next.
+__device__ __forceinline__ float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
 template <bool AK1, bool BK1>
 __device__ __forceinline__ void load_frags(const bf16* __restrict__ A, int64_t a_sm, int64_t a_sk,
