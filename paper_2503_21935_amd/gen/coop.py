@@ -54,8 +54,8 @@ class GGCoopEmitter(GGEmitter):
     relabelled by group element w and adds into the relabelled flows of J in LDS."""
 
     def __init__(self, name: str, n: int, merge: bool = True, cap: int = 12, window: int = 16,
-                 waves: int = 4, cap_f32: int = None):
-        super().__init__(name, n, merge, cap, cap_f32)
+                 waves: int = 4, cap_f32: int = None, opaque: str = "all"):
+        super().__init__(name, n, merge, cap, cap_f32, opaque)
         self.window = window
         self.waves = waves
         self.group = cyclic_group(n, waves)

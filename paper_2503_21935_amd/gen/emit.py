@@ -52,9 +52,11 @@ def emit_mfma_table(name, num):
 class GGEmitter:
     """g g -> t tbar + (n-2) gluons."""
 
-    def __init__(self, name: str, n: int, merge: bool = True, cap: int = 8, cap_f32: int = None):
+    def __init__(self, name: str, n: int, merge: bool = True, cap: int = 8, cap_f32: int = None,
+                 opaque: str = "all"):
         self.name = name
         self.cap = cap
+        self.opaque = opaque
         self.cap_f32 = cap_f32 if cap_f32 is not None else cap
         self.n = n
         self.plan = Plan(n, merge)
@@ -113,11 +115,22 @@ class GGEmitter:
             return "x.v4"
         return self.names[node]
 
+    # Operands pass through an opaque copy (opq) so that LLVM cannot merge
+    # subexpressions of one wavefunction across its uses and keep them alive
+    # in between.  opaque = "all": every wavefunction operand; "eps": only the
+    # external gluon polarisations, whose products are the ones worth keeping
+    # apart (the other operands' copies cost a 64-bit move each and, measured,
+    # more than the merging they prevent).
+    def _opq(self, s):
+        if self.opaque == "all" or (self.opaque == "eps" and s.startswith("x.eps[")):
+            return "opq(" + s + ")"
+        return s
+
     def cur(self, cid):
-        return "opq(" + self.sym(("c", cid)) + ")"
+        return self._opq(self.sym(("c", cid)))
 
     def osym(self, node):
-        return "opq(" + self.sym(node) + ")"
+        return self._opq(self.sym(node))
 
     def deps(self, node):
         kind = node[0]

@@ -24,10 +24,11 @@ from .plan import Plan
 
 
 class QEWEmitter(GGEmitter):
-    def __init__(self, name: str, spec: dict, merge: bool = True, cap: int = 12):
+    def __init__(self, name: str, spec: dict, merge: bool = True, cap: int = 12, opaque: str = "all"):
         self.name = name
         self.spec = spec
         self.cap = cap
+        self.opaque = opaque
         self.cap_f32 = cap
         self.n = spec["n"]
         self.plan = Plan(self.n, merge, ew=True)
