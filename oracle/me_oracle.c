@@ -13,7 +13,10 @@
  *   me2(p) = 1/(N_spin N_col S) * sum_helicities sum_colours |M(p)|^2
  *
  * written out from textbook tree-level Feynman rules, because the paper gives
- * no formulas.  Conventions (the readings are listed in the design notes):
+ * no formulas.  S = (n-2)! for the identical final gluons of g g -> t tbar +
+ * (n-2) g is parity unpinned: the GPU path applies the same reading and no
+ * closed form or limit checked here involves more than one final gluon.
+ * Conventions (the readings are listed in the design notes):
  *   metric (+,-,-,-); Dirac representation of the gamma matrices; helicity
  *   spinors and polarisation vectors built from polar angles; quark-gluon
  *   vertex  i g gamma^mu T^a;  three-gluon vertex  g f^{abc} V^{mu nu rho}
