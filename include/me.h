@@ -125,7 +125,8 @@ int me_set_precision(me_ctx *ctx, int mode, double rel_tol);
  * lanes-th filtered helicity and the lanes' partial sums are added when the
  * event is done.  lanes = 0 (the default): chosen per call, the smallest
  * power of two with nevt * lanes >= 65536, at most 64 and at most the number
- * of helicities kept (one lane per event from 65536 events up).  The result
+ * of helicities kept (one lane per event from 65536 events up), and at least
+ * a measured per-process floor (8 for "gg_ttgg", 1 otherwise).  The result
  * equals the one-lane result up to the order of the helicity sum.  Applies to
  * the float64 form of me_eval only (the mixed form, its float64 rerun,
  * me_eval_helicities and unweighting keep one lane per event).  Errors:
