@@ -21,8 +21,9 @@ GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # lane at 14); g g -> t tbar g g g (workgroup program, J in LDS, window of 16)
 # ran 334 ms per 2^18 events at 16 against 418 ms at 8 and 364 ms at 12 (18
 # and 20 spill more and gain nothing); with the cache-aware amplitude order
-# of the workgroup program it runs 304 ms at 16.
-LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14, "gg_ttggg": 16}
+# of the workgroup program it ran 304 ms at 16, and with opaque copies on the
+# polarisations only (OPAQUE below) 299 ms at 12.
+LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14, "gg_ttggg": 12}
 LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 # Processes whose colour-flow amplitudes are kept in LDS by a workgroup of
 # waves sharing one program (see coop.py): register window of J per wave.
@@ -31,8 +32,10 @@ COOP_WINDOW = {"gg_ttggg": 16}
 # polarisations only.  Measured per 2^20 events: g g -> t tbar g g 44.9 ms
 # against 49.2 ms with every operand opaque, g ubar -> tau+ tau- g g ubar
 # 8.8 ms against 9.5 ms; g g -> t tbar g g (with only the external
-# spinors or only the internal currents opaque) 46.0 and 56.6 ms.
-OPAQUE = {"gg_tt": "eps", "gg_ttg": "eps", "gg_ttgg": "eps", "gg_ttggg": "all"}
+# spinors or only the internal currents opaque) 46.0 and 56.6 ms; g g -> t
+# tbar g g g's workgroup program (with live-set cap 12 instead of 16) 299.4
+# ms per 2^18 events against 305.4 ms.
+OPAQUE = {"gg_tt": "eps", "gg_ttg": "eps", "gg_ttgg": "eps", "gg_ttggg": "eps"}
 QEW_OPAQUE = "eps"
 # Processes that also get the multi-channel program (single-diagram weights).
 MULTICHANNEL = {"gg_tt", "gg_ttg", "gg_ttgg"}
