@@ -16,14 +16,16 @@ GG_PROCESSES = {"gg_tt": 2, "gg_ttg": 3, "gg_ttgg": 4, "gg_ttggg": 5}
 # Maximum number of wavefunctions kept alive at once by the emitted program
 # (more are recomputed).  The momenta live in LDS, so the register budget
 # goes to wavefunctions and J.  Chosen per process by compiling and timing:
-# g g -> t tbar g g runs fastest at 14 (49.5 ms per 2^20 events against
-# 50.5 ms at 12, which has no private memory at all, and 44 bytes of it per
-# lane at 14); g g -> t tbar g g g (workgroup program, J in LDS, window of 16)
+# g g -> t tbar g g with every operand opaque ran fastest at 14 (49.5 ms per
+# 2^20 events against 50.5 ms at 12, which has no private memory at all, and
+# 44 bytes of it per lane at 14), with the polarisation-only copies at 13; g g -> t tbar g g g (workgroup program, J in LDS, window of 16)
 # ran 334 ms per 2^18 events at 16 against 418 ms at 8 and 364 ms at 12 (18
 # and 20 spill more and gain nothing); with the cache-aware amplitude order
 # of the workgroup program it ran 304 ms at 16, and with opaque copies on the
 # polarisations only (OPAQUE below) 299 ms at 12.
-LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14, "gg_ttggg": 12}
+LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 13, "gg_ttggg": 12}
+# the multi-channel programs (every operand opaque) keep the caps they were measured at
+MC_LIVE_CAP = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 14}
 LIVE_CAP_F32 = {"gg_tt": 8, "gg_ttg": 8, "gg_ttgg": 20, "gg_ttggg": 12}
 # Processes whose colour-flow amplitudes are kept in LDS by a workgroup of
 # waves sharing one program (see coop.py): register window of J per wave.
@@ -32,7 +34,9 @@ COOP_WINDOW = {"gg_ttggg": 16}
 # polarisations only.  Measured per 2^20 events: g g -> t tbar g g 44.9 ms
 # against 49.2 ms with every operand opaque, g ubar -> tau+ tau- g g ubar
 # 8.8 ms against 9.5 ms; g g -> t tbar g g (with only the external
-# spinors or only the internal currents opaque) 46.0 and 56.6 ms; g g -> t
+# spinors or only the internal currents opaque) 46.0 and 56.6 ms, and at cap
+# 13 instead of 14 1 % faster again with 196 instead of 268 B/lane of private
+# memory (45.8 against 46.5 ms at 8 helicity lanes on one box); g g -> t
 # tbar g g g's workgroup program (with live-set cap 12 instead of 16) 299.4
 # ms per 2^18 events against 305.4 ms.
 OPAQUE = {"gg_tt": "eps", "gg_ttg": "eps", "gg_ttgg": "eps", "gg_ttggg": "eps"}
@@ -90,7 +94,7 @@ def generate(outdir: str, processes=None, merge: bool = True) -> dict:
                 f.write(src)
         info[name] = dict(em.plan.stats(), lcd=em.lcd, ncol=len(em.perms))
         if name in MULTICHANNEL:
-            mc = GGEmitter(name, n, merge=False, cap=LIVE_CAP[name])
+            mc = GGEmitter(name, n, merge=False, cap=MC_LIVE_CAP[name])
             src = mc.render_mc()
             path = os.path.join(outdir, f"proc_{name}_mc.h")
             old = open(path).read() if os.path.exists(path) else None
