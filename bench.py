@@ -162,7 +162,10 @@ def bench_phase_space(me, stream, n, host_s):
     return {"workload": f"{n} g g -> t tbar g g points, sqrt(s) = 13 TeV", "kernel": "k_ps_rambo<4>",
             "points_per_s": n / k_s, "kernel_ms": k_s * 1e3,
             "roofline": {"bound": "hbm", "achieved": nbytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": 200},
+                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": 200,
+                         "note": "the output bytes against HBM; the kernel is bound by its float64 arithmetic "
+                                 "(Philox, logarithms, square roots, the massive rescaling), counted in "
+                                 "profiles/ps_rambo_2p20.md"},
             "host_numpy_rambo_s_same_size": host_s}
 
 
@@ -222,7 +225,9 @@ def bench_ps_multichannel(me, stream, n, steps):
                         f"alpha {alpha}", "kernel": f"k_ps_mc<{nf}>", "points_per_s": n / k_s,
             "kernel_ms": k_s * 1e3,
             "roofline": {"bound": "hbm", "achieved": nbytes / k_s / 1e9, "peak": 8000.0, "unit": "GB/s",
-                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": nbytes // n},
+                         "frac": nbytes / k_s / 1e9 / 8000.0, "bytes_per_point": nbytes // n,
+                         "note": "the output bytes against HBM; the kernel is bound by its float64 "
+                                 "transcendental functions, counted in profiles/ps_multichannel_dy3j_2p20.md"},
             "flat": fl, "multichannel": mc,
             "variance_gain": (fl["rel_std_error"] / mc["rel_std_error"]) ** 2,
             "estimates_differ_by_sigma": float(abs(fl["estimate"] - mc["estimate"]) / np.hypot(
